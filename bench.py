@@ -1,0 +1,252 @@
+"""Benchmark of the dense RISE patterns on one MI355X.
+
+A step is one pass of the timed workload: the FP32 GEMM C = A B with
+M = N = K = 4096 (A, B ~ U(-1,1)) followed by the 4096 x 4096 FP32 stencil with
+the 5 x 5 normalised Gaussian (sigma 1), clamp padding.  Inputs are resident
+in HBM before timing starts; the stencil rotates over several input/output
+buffer sets (more than the 256 MB last-level cache) so each launch reads HBM.
+
+One JSON line is printed.  Besides the contract fields it carries
+  roofline          GEMM kernel (dominant): algorithmic flops / event time
+  roofline_stencil  stencil kernel: algorithmic bytes (8 B per pixel) / event time
+  precision         8192^3 GEMM, N(0,1) 2^U(-4,4): time and componentwise error vs
+                    the exact product per mode, and the FP32 / BF16X3 speedup
+  cpu_baseline      the oracle on a bounded sample of the same workload
+Kernel times come from HIP events recorded on the stream the kernels run on.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
+PEAK_BF16 = 2516.6       # TFLOP/s dense
+PEAK_FP8 = 5033.0
+PEAK_HBM = 8000.0        # GB/s
+
+M = N = K = 4096
+H = W = 4096
+KS = 5
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--no-precision", action="store_true", help="skip the 8192^3 precision leg")
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    return p.parse_args()
+
+
+def src_hash(*rel):
+    h = hashlib.sha256()
+    for r in rel:
+        with open(os.path.join(ROOT, r), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, source_files, launches_per_unit=1):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    row = tab.get(kernel)
+    if not row or row.get("source_hash") != src_hash(*source_files):
+        return None
+    return row.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2201_03611_amd as rise
+    import rise_inputs as ri
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, device=dev, dtype=torch.float32)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4}))
+        return
+
+    # ---- inputs --------------------------------------------------------------
+    A, B = ri.gemm_uniform(M, N, K, ri.SEED_GEMM_F32)
+    img = ri.image_uniform(H, W, ri.SEED_STENCIL)
+    wts = ri.gaussian_weights(KS, 1.0)
+    dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    dC = torch.empty((M, N), device=dev, dtype=torch.float32)
+    nsets = 6  # 6 x 128 MiB > 256 MB last-level cache
+    imgs = [torch.from_numpy(img).to(dev) for _ in range(nsets)]
+    outs = [torch.empty((H, W), device=dev, dtype=torch.float32) for _ in range(nsets)]
+    dw = torch.from_numpy(wts).to(dev)
+    torch.cuda.synchronize()
+
+    def step(i, ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        rise.rise_gemm(dC, dA, dB, M, N, K, lda=K, ldb=N, ldc=N, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        s = i % nsets
+        rise.rise_stencil2d(outs[s], imgs[s], dw, H, W, ld_out=W, ld_in=W, kh=KS, kw=KS,
+                            pad="clamp", stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i, evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    t_gemm = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps  # ms
+    t_sten = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+
+    flops_gemm = 2.0 * M * N * K
+    flops_sten = 2.0 * KS * KS * H * W
+    bytes_sten = 8.0 * H * W
+    gemm_tf = flops_gemm / (t_gemm * 1e-3) / 1e12
+    sten_gbs = bytes_sten / (t_sten * 1e-3) / 1e9
+    value = (flops_gemm + flops_sten) / (ms_step * 1e-3) / 1e12
+
+    gemm_traffic = traffic_for("gemm_f32_kernel", ["paper_2201_03611_amd/csrc/gemm_f32.hip",
+                                                   "paper_2201_03611_amd/csrc/common.h"])
+    sten_traffic = traffic_for("stencil2d_tiled", ["paper_2201_03611_amd/csrc/stencil.hip",
+                                                   "paper_2201_03611_amd/csrc/common.h"])
+    result = {
+        "metric": "GEMM TFLOP/s + stencil GB/s vs roofline; BF16-comp vs FP32 speedup at equal error",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "FP32 GEMM 4096^3 U(-1,1) + FP32 stencil 4096x4096 5x5 Gaussian "
+                               "sigma=1 clamp", "gemm_mnk": [M, N, K], "stencil_hw": [H, W],
+                   "stencil_k": KS, "parallelism": "single-gpu"},
+        "gemm_tflops": round(gemm_tf, 2),
+        "stencil_gbps": round(sten_gbs, 1),
+        "roofline": {"bound": "mfma", "achieved": round(gemm_tf, 2), "peak": PEAK_FP32_MFMA,
+                     "unit": "TFLOP/s", "frac": round(gemm_tf / PEAK_FP32_MFMA, 4),
+                     "traffic": gemm_traffic, "kernel": "gemm_f32_kernel<128,128,32>",
+                     "ms": round(t_gemm, 4)},
+        "roofline_stencil": {"bound": "hbm", "achieved": round(sten_gbs, 1), "peak": PEAK_HBM,
+                             "unit": "GB/s", "frac": round(sten_gbs / PEAK_HBM, 4),
+                             "traffic": sten_traffic, "kernel": "stencil2d_tiled<5>",
+                             "ms": round(t_sten, 5)},
+    }
+
+    if not args.no_precision:
+        result["precision"] = precision_leg(rise, ri, np, torch, dev, stream)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_leg(ri, np, A, B, img, wts, value, ms_step)
+    print(json.dumps(result), flush=True)
+
+
+def precision_leg(rise, ri, np, torch, dev, stream):
+    """8192^3, N(0,1) 2^U(-4,4): every mode timed with events (operand preparation
+    included) and its componentwise error vs the exact product on sampled outputs."""
+    import oracle
+
+    n = 8192
+    A, B = ri.gemm_scaled_normal(n, n, n, ri.SEED_PRECISION)
+    rows, cols = ri.sample_indices(ri.rng(78), n, n, 600)
+    exact = oracle.gemm_sampled(A, B, rows, cols)
+    scale = oracle.gemm_sampled(np.abs(A), np.abs(B), rows, cols)
+    dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    dC = torch.empty((n, n), device=dev, dtype=torch.float32)
+    out = {}
+    peaks = {"f32": PEAK_FP32_MFMA, "bf16": PEAK_BF16, "bf16x3": PEAK_BF16, "bf16x6": PEAK_BF16,
+             "fp8": PEAK_FP8}
+    for mode in ["f32", "bf16", "bf16x3", "bf16x6", "fp8"]:
+        need = rise.rise_gemm_workspace(n, n, n, mode)
+        ws = torch.empty(max(need, 1), device=dev, dtype=torch.uint8)
+        call = lambda: rise.rise_gemm(dC, dA, dB, n, n, n, lda=n, ldb=n, ldc=n, mode=mode, ws=ws,
+                                      stream=stream)
+        call()
+        torch.cuda.synchronize()
+        reps = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        C = dC.cpu().numpy()[rows, cols]
+        err = float(np.max(np.abs(C.astype(np.float64) - exact) / scale))
+        tf = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        out[mode] = {"ms": round(ms, 3), "tflops_useful": round(tf, 1),
+                     "frac_of_own_peak": round(tf / peaks[mode], 4),
+                     "err_componentwise_max": err}
+        del ws
+    out["speedup_bf16x3_vs_f32"] = round(out["f32"]["ms"] / out["bf16x3"]["ms"], 3)
+    out["speedup_bf16x6_vs_f32"] = round(out["f32"]["ms"] / out["bf16x6"]["ms"], 3)
+    out["equal_error_bound"] = 1e-5
+    out["note"] = ("times include operand preparation; error = max over 604 sampled outputs of "
+                   "|c_hat - c| / (|A||B|)_ij against the exact product of the FP32 inputs")
+    return out
+
+
+def cpu_leg(ri, np, A, B, img, wts, gpu_value, ms_step):
+    """The oracle (fp64 view interpreter, OpenMP) on a bounded sample of the
+    step: 65536 sampled outputs of the 4096^3 GEMM and the full 4096^2 stencil,
+    rated in the metric's unit (flops of the sample / wall time)."""
+    import oracle
+
+    g = ri.rng(99)
+    rows, cols = ri.sample_indices(g, M, N, 65532)
+    t0 = time.perf_counter()
+    oracle.gemm_sampled(A, B, rows, cols)
+    t1 = time.perf_counter()
+    threads = oracle.last_threads()
+    oracle.stencil2d(img, wts)
+    t2 = time.perf_counter()
+    flops = 2.0 * K * rows.size + 2.0 * KS * KS * img.size
+    tflops = flops / (t2 - t0) / 1e12
+    return {"value": tflops, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows.size} of the 4096^2 GEMM outputs ({t1 - t0:.2f} s, "
+                      f"{2.0 * K * rows.size / (t1 - t0) / 1e9:.3f} GFLOP/s) + the full "
+                      f"4096^2 5x5 stencil ({t2 - t1:.2f} s, {8.0 * img.size / (t2 - t1) / 1e9:.3f} "
+                      f"GB/s)",
+            "gpu_over_cpu": round(gpu_value / tflops, 1)}
+
+
+if __name__ == "__main__":
+    main()

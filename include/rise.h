@@ -1,0 +1,154 @@
+/*
+ * rise.h -- C ABI of the MI355X (gfx950) library for the dense data-parallel
+ * patterns of RISE ("RISE & Shine: Language-Oriented Compiler Design",
+ * arXiv 2201.03611): the matrix product map(map(reduce . zip)) and the 2D
+ * stencil pad2D |> slide2D |> weighted reduce.
+ *
+ * Conventions shared by every entry point
+ *  - Outputs come first, then sizes, then inputs, mirroring the generated
+ *    kernel signature of the paper (Sec. V, OpenCL listing: restrict output,
+ *    sizes, restrict const inputs) and its dependent-function sizes-before-
+ *    arrays order (Sec. IV, matrix-vector program).
+ *  - The caller owns every buffer.  Array pointers are device pointers unless a
+ *    comment says otherwise.  The library allocates no device memory on these
+ *    paths; scratch space is passed in (`ws`, `ws_bytes`) and its size comes from
+ *    the matching *_workspace query.
+ *  - Outputs must not overlap inputs (the kernels' pointers are restrict).
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL is the null
+ *    stream).  Inputs must stay valid until the stream reaches the call.
+ *  - Nothing is chosen implicitly (Sec. V-B: a program whose memory choice is
+ *    missing is rejected, not completed by the compiler): an argument the
+ *    library has no kernel for is rejected with a status, and nothing is
+ *    enqueued.  rise_last_error() returns a thread-local description.
+ *  - Row-major storage everywhere; ld* are leading dimensions in elements.
+ *  - Sizes are int64_t; each dimension must be below 2^31.
+ */
+#ifndef RISE_H
+#define RISE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RISE_OK = 0,
+  RISE_ERR_NULL = 1,        /* a required pointer is NULL                         */
+  RISE_ERR_SHAPE = 2,       /* negative size, ld below the row length, size limit */
+  RISE_ERR_ALIAS = 3,       /* an output overlaps an input                        */
+  RISE_ERR_DTYPE = 4,       /* element type / mode combination has no kernel      */
+  RISE_ERR_UNSUPPORTED = 5, /* even or oversized window, unknown tile or mode     */
+  RISE_ERR_WORKSPACE = 6,   /* workspace missing or too small                     */
+  RISE_ERR_HIP = 7          /* the HIP runtime reported an error                  */
+} rise_status;
+
+/* storage element types of GEMM operands */
+typedef enum { RISE_F32 = 0, RISE_BF16 = 1 } rise_dtype;
+
+/* arithmetic of the GEMM contraction (always FP32 accumulation and FP32 C):
+ *  F32    : FP32 operands on the FP32 matrix cores
+ *  BF16   : operands rounded to bfloat16 (round to nearest even)
+ *  BF16X3 : each FP32 operand split a = hi + lo (hi = bf16(a), lo = bf16(a - hi));
+ *           C = Ah Bh + Ah Bl + Al Bh
+ *  BF16X6 : three-way split a = a1 + a2 + a3; the six products Ai Bj, i + j <= 4
+ *  FP8    : OCP E4M3 operands, one power-of-two scale per 32 consecutive K
+ *           elements of each row of A and each column of B                     */
+typedef enum {
+  RISE_MODE_F32 = 0,
+  RISE_MODE_BF16 = 1,
+  RISE_MODE_BF16X3 = 2,
+  RISE_MODE_BF16X6 = 3,
+  RISE_MODE_FP8 = 4
+} rise_mode;
+
+/* how an operand is read: as stored, or through transpose (a view, no copy) */
+typedef enum { RISE_OP_N = 0, RISE_OP_T = 1 } rise_op;
+
+/* boundary of pad2D: replicate the nearest edge element, or the constant 0 */
+typedef enum { RISE_PAD_CLAMP = 0, RISE_PAD_ZERO = 1 } rise_pad;
+
+/* An explicit schedule for one GEMM: the tile sizes produced by splitJoinMap
+ * on the two maps (bm, bn) and by split on the reduction (bk).  The paper keeps
+ * such choices outside the program, supplied by a strategy (Sec. IV-B/C); here
+ * the caller passes one or NULL, and NULL takes the library's default for the
+ * mode.  rise_gemm_tiles() lists the supported ones. */
+typedef struct {
+  int32_t bm, bn, bk;
+} rise_tile;
+
+const char* rise_status_string(rise_status s);
+
+/* Thread-local text of the last error raised on this thread ("" if none). */
+const char* rise_last_error(void);
+
+/* Number of supported tiles for `mode`; if `out` is non-NULL, up to `cap` of
+ * them are written there.  Host-only, enqueues nothing. */
+int32_t rise_gemm_tiles(rise_mode mode, rise_tile* out, int32_t cap);
+
+/* ------------------------------------------------------------------------ */
+/* GEMM                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of workspace rise_gemm needs for these sizes, mode and tile (NULL =
+ * default tile).  0 for RISE_MODE_F32, which reads its operands in place. */
+size_t rise_gemm_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode,
+                           const rise_tile* tile);
+
+/* C = A . B  (M x N, FP32, leading dimension ldc), with
+ *   A: M x K, read from storage of type tA through opA
+ *      (RISE_OP_N: stored M x K, element (i,k) at A[i*lda + k];
+ *       RISE_OP_T: stored K x M, element (i,k) at A[k*lda + i])
+ *   B: K x N, read through opB the same way (RISE_OP_T: stored N x K).
+ * Semantics: C = A |> map(aRow => transpose(B) |> map(bCol =>
+ *   zip(aRow, bCol) |> map(*) |> reduce(+, 0))), the paper's matrix-vector
+ * program (Sec. IV, running example) mapped over the columns of B, evaluated
+ * in the arithmetic of `mode`.  K = 0 writes C = 0 (reduce of an empty array is
+ * its initial value); M = 0 or N = 0 is a successful no-op.
+ * Types: mode F32 needs tA = tB = RISE_F32; BF16 accepts RISE_F32 (rounded)
+ * or RISE_BF16 operands; BF16X3, BF16X6 and FP8 need RISE_F32 operands.
+ * Workspace: at least rise_gemm_workspace(M, N, K, mode, tile) bytes, 256-byte
+ * aligned; it holds the prepared operands and is overwritten. */
+rise_status rise_gemm(float* C, int64_t ldc, const void* A, rise_dtype tA, int64_t lda,
+                      rise_op opA, const void* B, rise_dtype tB, int64_t ldb, rise_op opB,
+                      int64_t M, int64_t N, int64_t K, rise_mode mode, const rise_tile* tile,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Operand preparation of a reduced-precision mode (the map(cast) the mode's
+ * contraction consumes; map fusion, Sec. IV-B, lets it run as its own pass).
+ * The source holds `rows` vectors of length K; element k of vector r is
+ * src[r*ld_r + k*ld_k] (A row-major M x K: ld_r = lda, ld_k = 1; B row-major
+ * K x N: ld_r = 1, ld_k = ldb).  The destination holds `parts` planes (1 for
+ * BF16 and FP8, 2 for BF16X3, 3 for BF16X6), each rows_out x k_out,
+ * row-major, rows_out >= rows, k_out >= K; entries beyond (rows, K) are
+ * written as zero.  BF16 modes store bfloat16 bit patterns (2 bytes); FP8
+ * stores E4M3 bytes, followed by a scale plane of rows_out x (k_out / 32)
+ * E8M0 bytes (the dequantisation factor 2^(byte - 127) of each 32-element
+ * block; k_out must be a multiple of 32).  Bytes written:
+ * rise_prep_bytes(rows_out, k_out, mode). */
+size_t rise_prep_bytes(int64_t rows_out, int64_t k_out, rise_mode mode);
+rise_status rise_prep_operand(void* out, int64_t rows_out, int64_t k_out, const float* src,
+                              int64_t rows, int64_t K, int64_t ld_r, int64_t ld_k,
+                              rise_mode mode, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* 2D stencil                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* out = in |> pad2D(pad) |> slide2D(kh x kw, 1)
+ *          |> map(map(win => zip(join(win), join(w)) |> map(*) |> reduce(+, 0)))
+ * in: H x W FP32 (ld_in), out: H x W FP32 (ld_out), w: kh x kw FP32 weights,
+ * row-major, device memory.  Window element (dy, dx) of output (y, x) is
+ * input (y + dy - (kh-1)/2, x + dx - (kw-1)/2) (cross-correlation), outside
+ * the image either the nearest edge element (clamp) or 0 (zero).
+ * kh and kw must be odd and at most 15.  H = 0 or W = 0 is a no-op. */
+rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t ld_in,
+                           int64_t H, int64_t W, const float* w, int32_t kh, int32_t kw,
+                           rise_pad pad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RISE_H */

@@ -1,0 +1,157 @@
+"""Python binding of librise.so: MI355X kernels for the dense RISE patterns.
+
+Functions named rise_* mirror the C ABI (include/rise.h) one to one: they only
+marshal torch tensors (device memory) and the current HIP stream into the
+library call and raise RiseError on a non-OK status.  Every step of the
+computation runs in the library's HIP kernels.  The convenience wrappers
+(gemm, stencil2d, ...) allocate outputs and workspaces with torch and then
+call the same entry points.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (RISE_BF16, RISE_F32, RISE_MODE_BF16, RISE_MODE_BF16X3, RISE_MODE_BF16X6,
+                   RISE_MODE_F32, RISE_MODE_FP8, RISE_OP_N, RISE_OP_T, RISE_PAD_CLAMP,
+                   RISE_PAD_ZERO, RiseTile)
+
+lib = _lib.load()
+
+MODES = {"f32": RISE_MODE_F32, "bf16": RISE_MODE_BF16, "bf16x3": RISE_MODE_BF16X3,
+         "bf16x6": RISE_MODE_BF16X6, "fp8": RISE_MODE_FP8}
+PADS = {"clamp": RISE_PAD_CLAMP, "zero": RISE_PAD_ZERO}
+
+
+class RiseError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib.rise_last_error().decode()
+        super().__init__(f"{where}: {_lib.STATUS_NAMES.get(status, status)} ({msg})")
+
+
+def _check(status, where):
+    if status != _lib.RISE_OK:
+        raise RiseError(status, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mode(m):
+    return MODES[m] if isinstance(m, str) else int(m)
+
+
+def _tile(t):
+    if t is None:
+        return None
+    return ctypes.byref(RiseTile(*t))
+
+
+def _dtype(t):
+    if t.dtype == torch.float32:
+        return RISE_F32
+    if t.dtype == torch.bfloat16:
+        return RISE_BF16
+    raise TypeError(f"GEMM operands are float32 or bfloat16, got {t.dtype}")
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("librise works on device tensors only")
+
+
+# ---------------------------------------------------------------------------
+# one-to-one entry points
+# ---------------------------------------------------------------------------
+def rise_gemm_tiles(mode):
+    m = _mode(mode)
+    n = lib.rise_gemm_tiles(m, None, 0)
+    arr = (RiseTile * max(n, 1))()
+    lib.rise_gemm_tiles(m, arr, n)
+    return [(arr[i].bm, arr[i].bn, arr[i].bk) for i in range(n)]
+
+
+def rise_gemm_workspace(M, N, K, mode, tile=None):
+    return int(lib.rise_gemm_workspace(M, N, K, _mode(mode), _tile(tile)))
+
+
+def rise_gemm(C, A, B, M, N, K, *, lda, ldb, ldc, opA=RISE_OP_N, opB=RISE_OP_N, mode="f32",
+              tile=None, ws=None, stream=None):
+    """C (M x N, float32) = A . B; A, B device tensors read through opA / opB."""
+    _require_cuda(C, A, B, ws)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    st = lib.rise_gemm(_ptr(C), ldc, _ptr(A), _dtype(A), lda, opA, _ptr(B), _dtype(B), ldb, opB,
+                       M, N, K, _mode(mode), _tile(tile), _ptr(ws), ws_bytes, _stream(stream))
+    _check(st, "rise_gemm")
+
+
+def rise_prep_bytes(rows_out, k_out, mode):
+    return int(lib.rise_prep_bytes(rows_out, k_out, _mode(mode)))
+
+
+def rise_prep_operand(out, rows_out, k_out, src, rows, K, ld_r, ld_k, mode, stream=None):
+    _require_cuda(out, src)
+    st = lib.rise_prep_operand(_ptr(out), rows_out, k_out, _ptr(src), rows, K, ld_r, ld_k,
+                               _mode(mode), _stream(stream))
+    _check(st, "rise_prep_operand")
+
+
+def rise_stencil2d(out, inp, w, H, W, *, ld_out, ld_in, kh, kw, pad="clamp", stream=None):
+    _require_cuda(out, inp, w)
+    p = PADS[pad] if isinstance(pad, str) else int(pad)
+    st = lib.rise_stencil2d(_ptr(out), ld_out, _ptr(inp), ld_in, H, W, _ptr(w), kh, kw, p,
+                            _stream(stream))
+    _check(st, "rise_stencil2d")
+
+
+# ---------------------------------------------------------------------------
+# convenience wrappers
+# ---------------------------------------------------------------------------
+def gemm(A, B, *, transA=False, transB=False, mode="f32", tile=None, out=None, ws=None,
+         stream=None):
+    """Logical A (M x K) times logical B (K x N); transA means A is stored K x M."""
+    A = A.contiguous()
+    B = B.contiguous()
+    M, K = (A.shape[1], A.shape[0]) if transA else A.shape
+    K2, N = (B.shape[1], B.shape[0]) if transB else B.shape
+    if K != K2:
+        raise ValueError(f"inner sizes differ: {K} vs {K2}")
+    if out is None:
+        out = torch.empty((M, N), device=A.device, dtype=torch.float32)
+    need = rise_gemm_workspace(M, N, K, mode, tile)
+    if need and ws is None:
+        ws = torch.empty(need, device=A.device, dtype=torch.uint8)
+    rise_gemm(out, A, B, M, N, K, lda=A.shape[1], ldb=B.shape[1], ldc=out.stride(0),
+              opA=RISE_OP_T if transA else RISE_OP_N, opB=RISE_OP_T if transB else RISE_OP_N,
+              mode=mode, tile=tile, ws=ws, stream=stream)
+    return out
+
+
+def stencil2d(img, w, pad="clamp", out=None, stream=None):
+    img = img.contiguous()
+    w = w.contiguous().to(device=img.device, dtype=torch.float32)
+    H, W = img.shape
+    kh, kw = w.shape
+    if out is None:
+        out = torch.empty((H, W), device=img.device, dtype=torch.float32)
+    rise_stencil2d(out, img, w, H, W, ld_out=out.stride(0), ld_in=img.stride(0), kh=kh, kw=kw,
+                   pad=pad, stream=stream)
+    return out
+
+
+def prep_operand(src, mode, *, rows, K, ld_r, ld_k, rows_out=None, k_out=None, stream=None):
+    rows_out = rows if rows_out is None else rows_out
+    k_out = K if k_out is None else k_out
+    out = torch.empty(rise_prep_bytes(rows_out, k_out, mode), device=src.device,
+                      dtype=torch.uint8)
+    rise_prep_operand(out, rows_out, k_out, src, rows, K, ld_r, ld_k, mode, stream=stream)
+    return out

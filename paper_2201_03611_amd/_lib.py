@@ -1,0 +1,60 @@
+"""ctypes declarations of librise.so (the C ABI in include/rise.h).
+
+The library is loaded from this package directory.  There is no fallback: if
+librise.so is missing or fails to load, importing the package raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librise.so")
+
+RISE_OK = 0
+STATUS_NAMES = {0: "RISE_OK", 1: "RISE_ERR_NULL", 2: "RISE_ERR_SHAPE", 3: "RISE_ERR_ALIAS",
+                4: "RISE_ERR_DTYPE", 5: "RISE_ERR_UNSUPPORTED", 6: "RISE_ERR_WORKSPACE",
+                7: "RISE_ERR_HIP"}
+
+RISE_F32, RISE_BF16 = 0, 1
+RISE_MODE_F32, RISE_MODE_BF16, RISE_MODE_BF16X3, RISE_MODE_BF16X6, RISE_MODE_FP8 = 0, 1, 2, 3, 4
+RISE_OP_N, RISE_OP_T = 0, 1
+RISE_PAD_CLAMP, RISE_PAD_ZERO = 0, 1
+
+
+class RiseTile(ctypes.Structure):
+    _fields_ = [("bm", ctypes.c_int32), ("bn", ctypes.c_int32), ("bk", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SZ = ctypes.c_size_t
+_INT = ctypes.c_int
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "rise_status_string": (ctypes.c_char_p, [_INT]),
+    "rise_last_error": (ctypes.c_char_p, []),
+    "rise_gemm_tiles": (_I32, [_INT, ctypes.POINTER(RiseTile), _I32]),
+    "rise_gemm_workspace": (_SZ, [_I64, _I64, _I64, _INT, ctypes.POINTER(RiseTile)]),
+    "rise_gemm": (_INT, [_P, _I64, _P, _INT, _I64, _INT, _P, _INT, _I64, _INT, _I64, _I64, _I64,
+                         _INT, ctypes.POINTER(RiseTile), _P, _SZ, _P]),
+    "rise_prep_bytes": (_SZ, [_I64, _I64, _INT]),
+    "rise_prep_operand": (_INT, [_P, _I64, _I64, _P, _I64, _I64, _I64, _I64, _INT, _P]),
+    "rise_stencil2d": (_INT, [_P, _I64, _P, _I64, _I64, _I64, _P, _I32, _I32, _INT, _P]),
+}
+
+
+def load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python paper_2201_03611_amd/build.py` "
+                          "(or __graft_entry__.build()) first; there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def exported_names():
+    return list(SIGNATURES)

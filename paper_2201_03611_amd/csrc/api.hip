@@ -1,0 +1,201 @@
+// C ABI entry points: argument validation (before anything is enqueued) and
+// dispatch to the kernels.  Every rejected call names its reason through
+// rise_last_error(); nothing is chosen silently.
+#include <stdio.h>
+
+#include <algorithm>
+#include <string>
+
+#include "common.h"
+#include "gemm_lowp.h"
+
+namespace rise {
+
+static thread_local std::string g_last_error;
+
+rise_status fail(rise_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+rise_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(RISE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return RISE_OK;
+}
+
+namespace {
+
+constexpr int64_t kDimLimit = (int64_t)1 << 31;
+
+struct Range {
+  uintptr_t lo, hi;  // [lo, hi)
+};
+
+// Byte range touched by a rows x cols row-major array with leading dimension ld.
+Range span(const void* p, int64_t rows, int64_t cols, int64_t ld, int64_t esize) {
+  if (rows <= 0 || cols <= 0) return Range{0, 0};
+  uintptr_t lo = (uintptr_t)p;
+  return Range{lo, lo + (uintptr_t)(((rows - 1) * ld + cols) * esize)};
+}
+
+bool overlaps(Range a, Range b) {
+  if (a.lo == a.hi || b.lo == b.hi) return false;
+  return a.lo < b.hi && b.lo < a.hi;
+}
+
+bool dim_ok(int64_t v) { return v >= 0 && v < kDimLimit; }
+
+}  // namespace
+}  // namespace rise
+
+using namespace rise;
+
+extern "C" {
+
+const char* rise_status_string(rise_status s) {
+  switch (s) {
+    case RISE_OK: return "ok";
+    case RISE_ERR_NULL: return "null pointer";
+    case RISE_ERR_SHAPE: return "invalid shape or leading dimension";
+    case RISE_ERR_ALIAS: return "output overlaps an input";
+    case RISE_ERR_DTYPE: return "element type and mode have no kernel";
+    case RISE_ERR_UNSUPPORTED: return "unsupported argument";
+    case RISE_ERR_WORKSPACE: return "workspace missing or too small";
+    case RISE_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* rise_last_error(void) { return g_last_error.c_str(); }
+
+int32_t rise_gemm_tiles(rise_mode mode, rise_tile* out, int32_t cap) {
+  if (mode == RISE_MODE_F32) return gemm_f32_tiles(out, cap);
+  return gemm_lowp_tiles(mode, out, cap);
+}
+
+size_t rise_gemm_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode,
+                           const rise_tile* tile) {
+  if (mode == RISE_MODE_F32) return 0;
+  if (!dim_ok(M) || !dim_ok(N) || !dim_ok(K)) return 0;
+  rise_tile t = tile ? *tile : gemm_lowp_default_tile(mode, (int)M, (int)N, (int)K);
+  return gemm_lowp_workspace((int)M, (int)N, (int)K, mode, t);
+}
+
+rise_status rise_gemm(float* C, int64_t ldc, const void* A, rise_dtype tA, int64_t lda,
+                      rise_op opA, const void* B, rise_dtype tB, int64_t ldb, rise_op opB,
+                      int64_t M, int64_t N, int64_t K, rise_mode mode, const rise_tile* tile,
+                      void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!dim_ok(M) || !dim_ok(N) || !dim_ok(K))
+    return fail(RISE_ERR_SHAPE, "rise_gemm: sizes must be in [0, 2^31)");
+  if (opA != RISE_OP_N && opA != RISE_OP_T) return fail(RISE_ERR_UNSUPPORTED, "rise_gemm: opA");
+  if (opB != RISE_OP_N && opB != RISE_OP_T) return fail(RISE_ERR_UNSUPPORTED, "rise_gemm: opB");
+  if (mode < RISE_MODE_F32 || mode > RISE_MODE_FP8)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_gemm: unknown mode");
+  if (tA != RISE_F32 && tA != RISE_BF16) return fail(RISE_ERR_DTYPE, "rise_gemm: tA");
+  if (tB != RISE_F32 && tB != RISE_BF16) return fail(RISE_ERR_DTYPE, "rise_gemm: tB");
+  if (M == 0 || N == 0) return RISE_OK;
+  if (!C) return fail(RISE_ERR_NULL, "rise_gemm: C is NULL");
+  if (ldc < N) return fail(RISE_ERR_SHAPE, "rise_gemm: ldc < N");
+  // stored shapes of A and B
+  const int64_t ar = opA == RISE_OP_N ? M : K, ac = opA == RISE_OP_N ? K : M;
+  const int64_t br = opB == RISE_OP_N ? K : N, bc = opB == RISE_OP_N ? N : K;
+  if (K > 0) {
+    if (!A || !B) return fail(RISE_ERR_NULL, "rise_gemm: A or B is NULL");
+    if (lda < ac) return fail(RISE_ERR_SHAPE, "rise_gemm: lda below the stored row length");
+    if (ldb < bc) return fail(RISE_ERR_SHAPE, "rise_gemm: ldb below the stored row length");
+  }
+  const int64_t ea = tA == RISE_F32 ? 4 : 2, eb = tB == RISE_F32 ? 4 : 2;
+  Range rc = span(C, M, N, ldc, 4);
+  if (K > 0 && (overlaps(rc, span(A, ar, ac, lda, ea)) || overlaps(rc, span(B, br, bc, ldb, eb))))
+    return fail(RISE_ERR_ALIAS, "rise_gemm: C overlaps A or B");
+
+  if (mode == RISE_MODE_F32) {
+    if (tA != RISE_F32 || tB != RISE_F32)
+      return fail(RISE_ERR_DTYPE, "rise_gemm: mode F32 needs FP32 operands");
+    rise_tile t = tile ? *tile : gemm_f32_default_tile((int)M, (int)N, (int)K);
+    if (!gemm_f32_tile_supported(t))
+      return fail(RISE_ERR_UNSUPPORTED, "rise_gemm: tile not supported for mode F32");
+    GemmF32Args a{C, ldc, (const float*)A, lda, (const float*)B, ldb, (int)M, (int)N, (int)K,
+                  opA == RISE_OP_T, opB == RISE_OP_T};
+    return launch_gemm_f32(a, t, (hipStream_t)stream);
+  }
+
+  if (mode != RISE_MODE_BF16 && (tA != RISE_F32 || tB != RISE_F32))
+    return fail(RISE_ERR_DTYPE, "rise_gemm: split and FP8 modes need FP32 operands");
+  rise_tile t = tile ? *tile : gemm_lowp_default_tile(mode, (int)M, (int)N, (int)K);
+  if (!gemm_lowp_tile_supported(mode, t))
+    return fail(RISE_ERR_UNSUPPORTED, "rise_gemm: tile not supported for this mode");
+  size_t need = gemm_lowp_workspace((int)M, (int)N, (int)K, mode, t);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(RISE_ERR_WORKSPACE, "rise_gemm: workspace below rise_gemm_workspace()");
+  if (need > 0 && ((uintptr_t)ws & 255))
+    return fail(RISE_ERR_WORKSPACE, "rise_gemm: workspace must be 256-byte aligned");
+  if (need > 0) {
+    Range rw{(uintptr_t)ws, (uintptr_t)ws + need};
+    if (overlaps(rw, rc) || (K > 0 && (overlaps(rw, span(A, ar, ac, lda, ea)) ||
+                                       overlaps(rw, span(B, br, bc, ldb, eb)))))
+      return fail(RISE_ERR_ALIAS, "rise_gemm: workspace overlaps C, A or B");
+  }
+  GemmLowpArgs a{C, ldc, A, tA, lda, opA == RISE_OP_T, B, tB, ldb, opB == RISE_OP_T,
+                 (int)M, (int)N, (int)K, mode};
+  return launch_gemm_lowp(a, t, ws, (hipStream_t)stream);
+}
+
+size_t rise_prep_bytes(int64_t rows_out, int64_t k_out, rise_mode mode) {
+  if (rows_out < 0 || k_out < 0) return 0;
+  return prep_bytes(rows_out, k_out, mode);
+}
+
+rise_status rise_prep_operand(void* out, int64_t rows_out, int64_t k_out, const float* src,
+                              int64_t rows, int64_t K, int64_t ld_r, int64_t ld_k,
+                              rise_mode mode, void* stream) {
+  clear_error();
+  if (mode != RISE_MODE_BF16 && mode != RISE_MODE_BF16X3 && mode != RISE_MODE_BF16X6 &&
+      mode != RISE_MODE_FP8)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_prep_operand: mode has no preparation");
+  if (!dim_ok(rows) || !dim_ok(K) || !dim_ok(rows_out) || !dim_ok(k_out))
+    return fail(RISE_ERR_SHAPE, "rise_prep_operand: sizes must be in [0, 2^31)");
+  if (rows_out < rows || k_out < K)
+    return fail(RISE_ERR_SHAPE, "rise_prep_operand: destination smaller than the source");
+  if (mode == RISE_MODE_FP8 && k_out % 32 != 0)
+    return fail(RISE_ERR_SHAPE, "rise_prep_operand: FP8 needs k_out a multiple of 32");
+  if (ld_r < 0 || ld_k < 0) return fail(RISE_ERR_SHAPE, "rise_prep_operand: negative stride");
+  if (rows_out == 0 || k_out == 0) return RISE_OK;
+  if (!out) return fail(RISE_ERR_NULL, "rise_prep_operand: out is NULL");
+  if (rows > 0 && K > 0) {
+    if (!src) return fail(RISE_ERR_NULL, "rise_prep_operand: src is NULL");
+    uintptr_t lo = (uintptr_t)src;
+    uintptr_t hi = lo + (uintptr_t)(((rows - 1) * ld_r + (K - 1) * ld_k + 1) * 4);
+    Range ro{(uintptr_t)out, (uintptr_t)out + prep_bytes(rows_out, k_out, mode)};
+    if (overlaps(ro, Range{lo, hi})) return fail(RISE_ERR_ALIAS, "rise_prep_operand: overlap");
+  }
+  PrepArgs a{out, rows_out, k_out, src, rows, K, ld_r, ld_k, mode};
+  return launch_prep(a, (hipStream_t)stream);
+}
+
+rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t ld_in,
+                           int64_t H, int64_t W, const float* w, int32_t kh, int32_t kw,
+                           rise_pad pad, void* stream) {
+  clear_error();
+  if (!dim_ok(H) || !dim_ok(W) || H * W >= kDimLimit * 2)
+    return fail(RISE_ERR_SHAPE, "rise_stencil2d: sizes must be in [0, 2^31)");
+  if (kh <= 0 || kw <= 0 || kh % 2 == 0 || kw % 2 == 0 || kh > 15 || kw > 15)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d: window sides must be odd and <= 15");
+  if (pad != RISE_PAD_CLAMP && pad != RISE_PAD_ZERO)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d: unknown pad mode");
+  if (H == 0 || W == 0) return RISE_OK;
+  if (!out || !in || !w) return fail(RISE_ERR_NULL, "rise_stencil2d: NULL pointer");
+  if (ld_in < W || ld_out < W) return fail(RISE_ERR_SHAPE, "rise_stencil2d: ld below W");
+  Range ro = span(out, H, W, ld_out, 4);
+  if (overlaps(ro, span(in, H, W, ld_in, 4)) || overlaps(ro, span(w, kh, kw, kw, 4)))
+    return fail(RISE_ERR_ALIAS, "rise_stencil2d: out overlaps in or w");
+  StencilArgs a{out, ld_out, in, ld_in, (int)H, (int)W, w, kh, kw, (int)pad};
+  return launch_stencil2d(a, (hipStream_t)stream);
+}
+
+}  // extern "C"

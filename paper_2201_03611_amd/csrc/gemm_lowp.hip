@@ -1,0 +1,392 @@
+// Reduced-precision GEMM on the gfx950 matrix cores, FP32 accumulation.
+//
+// The operands arrive prepared (prep.hip): A as Mp x Kp rows and B as Np x Kp
+// rows of transpose(B), K contiguous and zero padded to whole tiles, so the K
+// loop needs no bounds checks (zero padding adds exact zeros to the sum).
+//
+// Pattern -> hardware mapping (paper Sec. IV-B/C, V-C):
+//   split(BM) / split(BN) + mapWorkGroup -> one workgroup per BM x BN tile of C
+//   mapLocal                             -> 2 x 2 waves, each (BM/2) x (BN/2)
+//   split(BK) + reduceSeq(Private)       -> K loop, accumulators in registers
+//   toMem(Local)                         -> double-buffered LDS slabs; 16-byte
+//                                           chunks XOR-swizzled by row so the
+//                                           fragment reads are conflict free
+//   zip |> map(*) |> reduce(+)           -> v_mfma_f32_32x32x16_bf16, or
+//                                           v_mfma_scale_f32_32x32x64_f8f6f4
+//                                           with the E8M0 block scales applied
+//                                           inside the instruction
+//   split compensation                   -> the extra products (hi.lo, lo.hi,
+//                                           ...) accumulate into the same
+//                                           registers: no extra pass over C.
+#include "gemm_lowp.h"
+
+namespace rise {
+namespace {
+
+constexpr int kThreads = 256;
+
+// row r, 16-byte chunk c of a slab with CH chunks per row -> chunk index in LDS
+template <int CH>
+__device__ __forceinline__ int swz(int r, int c) {
+  constexpr int per = 8 / CH;  // rows sharing one 128-byte bank line
+  return r * CH + (c ^ ((r / per) % CH));
+}
+
+template <int MODE>
+struct Parts {
+  static constexpr int n = MODE == RISE_MODE_BF16 ? 1 : MODE == RISE_MODE_BF16X3 ? 2 : 3;
+  // kept products (part of A, part of B): parts i, j with i + j <= n - 1
+  static constexpr int nprod = n == 1 ? 1 : n == 2 ? 3 : 6;
+  __device__ static constexpr int pa(int q) {
+    constexpr int a[6] = {0, 0, 1, 0, 1, 2};
+    return a[q];
+  }
+  __device__ static constexpr int pb(int q) {
+    constexpr int b[6] = {0, 1, 0, 2, 1, 0};
+    return b[q];
+  }
+};
+
+template <int BM, int BN, int BK, int MODE>
+__global__ __launch_bounds__(kThreads, 1) void packed_bf16_kernel(
+    float* __restrict__ C, int64_t ldc, const uint16_t* __restrict__ Ap,
+    const uint16_t* __restrict__ Bp, int M, int N, int Kp, int Mp, int Np, int tiles_m,
+    int tiles_n) {
+  using P = Parts<MODE>;
+  constexpr int NP = P::n;
+  constexpr int CH = BK / 8;                 // 16-byte chunks per slab row
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 32, TN = WN / 32;
+  constexpr int LA = BM * BK / 8 / kThreads;  // chunks per thread per part
+  constexpr int LB = BN * BK / 8 / kThreads;
+  static_assert(LA >= 1 && LB >= 1, "tile too small");
+
+  __shared__ i32x4 As[2][NP][BM * CH];
+  __shared__ i32x4 Bs[2][NP][BN * CH];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+  int tm, tn;
+  grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, 4, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int64_t planeA = (int64_t)Mp * Kp, planeB = (int64_t)Np * Kp;
+
+  i32x4 ra[NP][LA], rb[NP][LB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+#pragma unroll
+      for (int q = 0; q < LA; q++) {
+        int c = tid + kThreads * q, r = c / CH, ch = c % CH;
+        ra[p][q] = *reinterpret_cast<const i32x4*>(Ap + p * planeA + (int64_t)(m0 + r) * Kp + k0 + ch * 8);
+      }
+#pragma unroll
+      for (int q = 0; q < LB; q++) {
+        int c = tid + kThreads * q, r = c / CH, ch = c % CH;
+        rb[p][q] = *reinterpret_cast<const i32x4*>(Bp + p * planeB + (int64_t)(n0 + r) * Kp + k0 + ch * 8);
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+#pragma unroll
+      for (int q = 0; q < LA; q++) {
+        int c = tid + kThreads * q;
+        As[buf][p][swz<CH>(c / CH, c % CH)] = ra[p][q];
+      }
+#pragma unroll
+      for (int q = 0; q < LB; q++) {
+        int c = tid + kThreads * q;
+        Bs[buf][p][swz<CH>(c / CH, c % CH)] = rb[p][q];
+      }
+    }
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  const int nk = Kp / BK;
+  if (nk > 0) {
+    fetch(0);
+    stash(0);
+    __syncthreads();
+  }
+  const int il = lane & 31, kh = lane >> 5;
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) fetch((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ks++) {
+      const int c = 2 * ks + kh;  // this lane's 8 consecutive k within the slab
+      bf16x8 a[NP][TM], b[NP][TN];
+#pragma unroll
+      for (int p = 0; p < NP; p++) {
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+          a[p][i] = __builtin_bit_cast(bf16x8, As[cur][p][swz<CH>(wm0 + 32 * i + il, c)]);
+#pragma unroll
+        for (int j = 0; j < TN; j++)
+          b[p][j] = __builtin_bit_cast(bf16x8, Bs[cur][p][swz<CH>(wn0 + 32 * j + il, c)]);
+      }
+#pragma unroll
+      for (int q = P::nprod - 1; q >= 0; q--)  // small products first
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+#pragma unroll
+          for (int j = 0; j < TN; j++)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[P::pa(q)][i], b[P::pb(q)][j],
+                                                                acc[i][j], 0, 0, 0);
+    }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+      const int col = n0 + wn0 + j * 32 + il;
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// FP8 E4M3 with E8M0 block scales (32 elements along K per scale).
+template <int BM, int BN>
+__global__ __launch_bounds__(kThreads, 1) void packed_fp8_kernel(
+    float* __restrict__ C, int64_t ldc, const uint8_t* __restrict__ Ap,
+    const uint8_t* __restrict__ Bp, int M, int N, int Kp, int Mp, int Np, int tiles_m,
+    int tiles_n) {
+  constexpr int BK = 128;                      // bytes = elements per slab row
+  constexpr int CH = BK / 16;                  // 8 chunks
+  constexpr int SB = BK / 32;                  // scale bytes per slab row
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
+  constexpr int LA = BM * CH / kThreads, LB = BN * CH / kThreads;
+  static_assert(BM <= kThreads && BN <= kThreads, "one scale word per thread");
+
+  __shared__ i32x4 As[2][BM * CH];
+  __shared__ i32x4 Bs[2][BN * CH];
+  __shared__ uint32_t Asc[2][BM];  // SB = 4 scale bytes of a row packed in one word
+  __shared__ uint32_t Bsc[2][BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+  int tm, tn;
+  grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, 4, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const uint8_t* As_g = Ap + (int64_t)Mp * Kp;  // scale planes follow the code planes
+  const uint8_t* Bs_g = Bp + (int64_t)Np * Kp;
+  const int sstride = Kp / 32;
+
+  i32x4 ra[LA], rb[LB];
+  uint32_t sa = 0, sb = 0;
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < LA; q++) {
+      int c = tid + kThreads * q, r = c / CH, ch = c % CH;
+      ra[q] = *reinterpret_cast<const i32x4*>(Ap + (int64_t)(m0 + r) * Kp + k0 + ch * 16);
+    }
+#pragma unroll
+    for (int q = 0; q < LB; q++) {
+      int c = tid + kThreads * q, r = c / CH, ch = c % CH;
+      rb[q] = *reinterpret_cast<const i32x4*>(Bp + (int64_t)(n0 + r) * Kp + k0 + ch * 16);
+    }
+    if (tid < BM) sa = *reinterpret_cast<const uint32_t*>(As_g + (int64_t)(m0 + tid) * sstride + k0 / 32);
+    if (tid < BN) sb = *reinterpret_cast<const uint32_t*>(Bs_g + (int64_t)(n0 + tid) * sstride + k0 / 32);
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < LA; q++) {
+      int c = tid + kThreads * q;
+      As[buf][swz<CH>(c / CH, c % CH)] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LB; q++) {
+      int c = tid + kThreads * q;
+      Bs[buf][swz<CH>(c / CH, c % CH)] = rb[q];
+    }
+    if (tid < BM) Asc[buf][tid] = sa;
+    if (tid < BN) Bsc[buf][tid] = sb;
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  const int nk = Kp / BK;
+  if (nk > 0) {
+    fetch(0);
+    stash(0);
+    __syncthreads();
+  }
+  const int il = lane & 31, kh = lane >> 5;
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) fetch((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 64; ks++) {
+      // lane supplies 32 consecutive k: slab bytes 64*ks + 32*kh .. +31 (2 chunks),
+      // which form scale block 2*ks + kh of its row
+      const int c0 = 4 * ks + 2 * kh;
+      const int sh = 8 * (2 * ks + kh);
+      i32x8 a[TM], b[TN];
+      int xa[TM], xb[TN];
+#pragma unroll
+      for (int i = 0; i < TM; i++) {
+        const int r = wm0 + 32 * i + il;
+        i32x4 lo = As[cur][swz<CH>(r, c0)], hi = As[cur][swz<CH>(r, c0 + 1)];
+        a[i] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        xa[i] = (int)((Asc[cur][r] >> sh) & 0xffu);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; j++) {
+        const int r = wn0 + 32 * j + il;
+        i32x4 lo = Bs[cur][swz<CH>(r, c0)], hi = Bs[cur][swz<CH>(r, c0 + 1)];
+        b[j] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        xb[j] = (int)((Bsc[cur][r] >> sh) & 0xffu);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
+                                                                     0, xa[i], 0, xb[j]);
+    }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+      const int col = n0 + wn0 + j * 32 + il;
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+struct TileRow {
+  rise_mode mode;
+  rise_tile t;
+};
+const TileRow kTiles[] = {
+    {RISE_MODE_BF16, {256, 256, 64}},   {RISE_MODE_BF16, {128, 128, 64}},
+    {RISE_MODE_BF16X3, {256, 256, 32}}, {RISE_MODE_BF16X3, {128, 128, 32}},
+    {RISE_MODE_BF16X6, {256, 256, 16}}, {RISE_MODE_BF16X6, {128, 128, 16}},
+    {RISE_MODE_FP8, {256, 256, 128}},   {RISE_MODE_FP8, {128, 128, 128}},
+};
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+template <int BM, int BN, int BK, int MODE>
+rise_status launch_bf16(const PackedGemm& g, hipStream_t s) {
+  int tiles_m = g.Mp / BM, tiles_n = g.Np / BN;
+  hipLaunchKernelGGL((packed_bf16_kernel<BM, BN, BK, MODE>), dim3(tiles_m * tiles_n),
+                     dim3(kThreads), 0, s, g.C, g.ldc, (const uint16_t*)g.Ap,
+                     (const uint16_t*)g.Bp, g.M, g.N, g.Kp, g.Mp, g.Np, tiles_m, tiles_n);
+  return check_launch("packed_bf16_kernel");
+}
+
+template <int BM, int BN>
+rise_status launch_fp8(const PackedGemm& g, hipStream_t s) {
+  int tiles_m = g.Mp / BM, tiles_n = g.Np / BN;
+  hipLaunchKernelGGL((packed_fp8_kernel<BM, BN>), dim3(tiles_m * tiles_n), dim3(kThreads), 0, s,
+                     g.C, g.ldc, (const uint8_t*)g.Ap, (const uint8_t*)g.Bp, g.M, g.N, g.Kp, g.Mp,
+                     g.Np, tiles_m, tiles_n);
+  return check_launch("packed_fp8_kernel");
+}
+
+}  // namespace
+
+int gemm_lowp_tiles(rise_mode mode, rise_tile* out, int cap) {
+  int n = 0;
+  for (const auto& r : kTiles)
+    if (r.mode == mode) {
+      if (out && n < cap) out[n] = r.t;
+      n++;
+    }
+  return n;
+}
+
+bool gemm_lowp_tile_supported(rise_mode mode, const rise_tile& t) {
+  for (const auto& r : kTiles)
+    if (r.mode == mode && r.t.bm == t.bm && r.t.bn == t.bn && r.t.bk == t.bk) return true;
+  return false;
+}
+
+rise_tile gemm_lowp_default_tile(rise_mode mode, int M, int N, int K) {
+  rise_tile big{}, small{};
+  int seen = 0;
+  for (const auto& r : kTiles)
+    if (r.mode == mode) {
+      if (seen == 0) big = r.t;
+      else small = r.t;
+      seen++;
+    }
+  long tiles_big = (long)((M + big.bm - 1) / big.bm) * ((N + big.bn - 1) / big.bn);
+  return tiles_big >= 256 ? big : small;
+}
+
+size_t gemm_lowp_workspace(int M, int N, int K, rise_mode mode, const rise_tile& t) {
+  int64_t Mp = round_up(M, t.bm), Np = round_up(N, t.bn), Kp = round_up(K, t.bk);
+  return (size_t)round_up((int64_t)prep_bytes(Mp, Kp, mode), 256) + prep_bytes(Np, Kp, mode);
+}
+
+rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStream_t s) {
+  switch (g.mode) {
+    case RISE_MODE_BF16:
+      if (t.bm == 256) return launch_bf16<256, 256, 64, RISE_MODE_BF16>(g, s);
+      return launch_bf16<128, 128, 64, RISE_MODE_BF16>(g, s);
+    case RISE_MODE_BF16X3:
+      if (t.bm == 256) return launch_bf16<256, 256, 32, RISE_MODE_BF16X3>(g, s);
+      return launch_bf16<128, 128, 32, RISE_MODE_BF16X3>(g, s);
+    case RISE_MODE_BF16X6:
+      if (t.bm == 256) return launch_bf16<256, 256, 16, RISE_MODE_BF16X6>(g, s);
+      return launch_bf16<128, 128, 16, RISE_MODE_BF16X6>(g, s);
+    case RISE_MODE_FP8:
+      if (t.bm == 256) return launch_fp8<256, 256>(g, s);
+      return launch_fp8<128, 128>(g, s);
+    default:
+      return fail(RISE_ERR_UNSUPPORTED, "packed gemm: mode");
+  }
+}
+
+rise_status launch_gemm_lowp(const GemmLowpArgs& a, const rise_tile& t, void* ws, hipStream_t s) {
+  const int64_t Mp = round_up(a.M, t.bm), Np = round_up(a.N, t.bn), Kp = round_up(a.K, t.bk);
+  uint8_t* wsA = (uint8_t*)ws;
+  uint8_t* wsB = wsA + round_up((int64_t)prep_bytes(Mp, Kp, a.mode), 256);
+  // A: M vectors of length K; B: N vectors of length K (columns of B)
+  PrepArgs pa{wsA, Mp, Kp, a.A, a.M, a.K, a.ta ? 1 : a.lda, a.ta ? a.lda : 1, a.mode,
+              a.tA == RISE_BF16};
+  PrepArgs pb{wsB, Np, Kp, a.B, a.N, a.K, a.tb ? a.ldb : 1, a.tb ? 1 : a.ldb, a.mode,
+              a.tB == RISE_BF16};
+  rise_status st = launch_prep(pa, s);
+  if (st != RISE_OK) return st;
+  st = launch_prep(pb, s);
+  if (st != RISE_OK) return st;
+  PackedGemm g{a.C, a.ldc, wsA, wsB, a.M, a.N, (int)Kp, (int)Mp, (int)Np, a.mode};
+  return launch_packed_gemm(g, t, s);
+}
+
+}  // namespace rise

@@ -1,0 +1,271 @@
+// Operand preparation for the reduced-precision GEMM modes: map(cast) over an
+// operand, materialised once (toMem, paper Sec. V-B) in the K-contiguous,
+// zero-padded layout the matrix-core kernels read.  B is read through
+// transpose here, so the contraction kernels see transpose(B) rows.
+//
+//   BF16   : bf16(a), round to nearest even
+//   BF16X3 : hi = bf16(a), lo = bf16(a - hi)            (a - hi is exact in f32)
+//   BF16X6 : a1 = bf16(a), a2 = bf16(a - a1), a3 = bf16(a - a1 - a2)
+//   FP8    : per 32-element block along K: e = largest integer with
+//            amax * 2^e <= 448 (0 for an all-zero block), q = e4m3(a * 2^e)
+//            (round to nearest even), scale byte 127 - e (E8M0 of 2^-e).
+//
+// Each workgroup transposes a 64 x 64 (rows x K) tile through LDS so that both
+// the read (along whichever source dimension is contiguous) and the write
+// (along K) are coalesced.
+#include "gemm_lowp.h"
+
+namespace rise {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int TR = 64;  // rows per tile
+constexpr int TK = 64;  // K per tile
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  // round to nearest even on the f32 bit pattern; NaN stays a quiet NaN
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// E4M3 (OCP, bias 7, no infinities) of a value with |v| <= 448, round to
+// nearest even.  Normal range: 3 mantissa bits below the leading one;
+// below 2^-6 the quantum is fixed at 2^-9.
+__device__ __forceinline__ uint8_t e4m3_rne(float v) {
+  uint32_t u = __float_as_uint(v);
+  uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+  uint32_t a = u & 0x7fffffffu;
+  int ef = (int)(a >> 23);          // f32 exponent field
+  if (ef < 127 - 6) {               // |v| < 2^-6: subnormal target, quantum 2^-9
+    // v / 2^-9 rounded to nearest even, exact in f32 arithmetic for this range
+    float q = __uint_as_float(a) * 512.0f;
+    float r = __builtin_rintf(q);   // current rounding mode: nearest even
+    uint32_t m = (uint32_t)r;       // 0..8; 8 means the smallest normal (exp field 1)
+    return (uint8_t)(sign | m);
+  }
+  // normal: keep 3 mantissa bits, RNE on the remaining 20
+  uint32_t mant = a & 0x7fffffu;
+  uint32_t keep = mant >> 20, rest = mant & 0xfffffu;
+  uint32_t half = 0x80000u;
+  if (rest > half || (rest == half && (keep & 1u))) keep++;
+  int e = ef - 127 + 7;
+  if (keep == 8u) {  // mantissa overflow carries into the exponent
+    keep = 0;
+    e++;
+  }
+  return (uint8_t)(sign | (uint8_t)(e << 3) | (uint8_t)keep);
+}
+
+// Largest e with amax * 2^e <= 448 (= 1.75 * 2^8), from the f32 fields of amax;
+// 0 for amax = 0; at most 127.
+__device__ __forceinline__ int e4m3_block_exp(float amax) {
+  uint32_t a = __float_as_uint(amax) & 0x7fffffffu;
+  if (a == 0) return 0;
+  int ef = (int)(a >> 23);
+  if (ef == 0) return 127;  // f32 subnormal amax: any e up to 127 fits
+  uint32_t mant = a & 0x7fffffu;
+  int e = (mant <= 0x600000u ? 135 : 134) - ef;
+  return e > 127 ? 127 : e;
+}
+
+template <typename SRC>
+__device__ __forceinline__ float load_src(const SRC* p);
+template <>
+__device__ __forceinline__ float load_src<float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float load_src<uint16_t>(const uint16_t* p) { return bf16_to_f32(*p); }
+
+// layout: 0 = strided scalar loads, 1 = K contiguous (ld_k == 1) with float4,
+// 2 = rows contiguous (ld_r == 1) with float4
+template <typename SRC, int MODE, int LAYOUT>
+__global__ __launch_bounds__(kThreads) void prep_kernel(void* __restrict__ out, int64_t rows_out,
+                                                        int64_t k_out,
+                                                        const SRC* __restrict__ src,
+                                                        int64_t rows, int64_t K, int64_t ld_r,
+                                                        int64_t ld_k, int vec_out) {
+  __shared__ float tile[TR][TK + 1];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * TR;
+  const int64_t k0 = (int64_t)blockIdx.y * TK;
+
+  // ---- load the source tile (zeros outside rows x K) ----------------------
+  if (LAYOUT == 1) {
+#pragma unroll
+    for (int p = 0; p < TR * TK / 4 / kThreads; p++) {
+      int c = tid + kThreads * p;
+      int row = c / (TK / 4), kk = (c % (TK / 4)) * 4;
+      int64_t gr = r0 + row, gk = k0 + kk;
+      f32x4 v = {0.f, 0.f, 0.f, 0.f};
+      if (gr < rows) {
+        const float* q = reinterpret_cast<const float*>(src) + gr * ld_r + gk;
+        if (gk + 3 < K) {
+          v = *reinterpret_cast<const f32x4*>(q);
+        } else {
+          if (gk + 0 < K) v.x = q[0];
+          if (gk + 1 < K) v.y = q[1];
+          if (gk + 2 < K) v.z = q[2];
+        }
+      }
+      tile[row][kk + 0] = v.x;
+      tile[row][kk + 1] = v.y;
+      tile[row][kk + 2] = v.z;
+      tile[row][kk + 3] = v.w;
+    }
+  } else if (LAYOUT == 2) {
+#pragma unroll
+    for (int p = 0; p < TR * TK / 4 / kThreads; p++) {
+      int c = tid + kThreads * p;
+      int kk = c / (TR / 4), row = (c % (TR / 4)) * 4;
+      int64_t gr = r0 + row, gk = k0 + kk;
+      f32x4 v = {0.f, 0.f, 0.f, 0.f};
+      if (gk < K) {
+        const float* q = reinterpret_cast<const float*>(src) + gk * ld_k + gr;
+        if (gr + 3 < rows) {
+          v = *reinterpret_cast<const f32x4*>(q);
+        } else {
+          if (gr + 0 < rows) v.x = q[0];
+          if (gr + 1 < rows) v.y = q[1];
+          if (gr + 2 < rows) v.z = q[2];
+        }
+      }
+      tile[row + 0][kk] = v.x;
+      tile[row + 1][kk] = v.y;
+      tile[row + 2][kk] = v.z;
+      tile[row + 3][kk] = v.w;
+    }
+  } else {
+    for (int c = tid; c < TR * TK; c += kThreads) {
+      int row = c / TK, kk = c % TK;
+      int64_t gr = r0 + row, gk = k0 + kk;
+      tile[row][kk] = (gr < rows && gk < K) ? load_src<SRC>(src + gr * ld_r + gk * ld_k) : 0.f;
+    }
+  }
+  __syncthreads();
+
+  // ---- convert 16 consecutive K of one row per thread ----------------------
+  const int row = tid / 4, kc = (tid % 4) * 16;
+  const int64_t gr = r0 + row, gk = k0 + kc;
+  if (gr >= rows_out) return;  // (no barrier follows)
+  float x[16];
+#pragma unroll
+  for (int e = 0; e < 16; e++) x[e] = tile[row][kc + e];
+  const bool full = gk + 16 <= k_out;
+
+  if (MODE == RISE_MODE_FP8) {
+    float amax = 0.f;
+#pragma unroll
+    for (int e = 0; e < 16; e++) amax = fmaxf(amax, fabsf(x[e]));
+    amax = fmaxf(amax, __shfl_xor(amax, 1));  // the 32-element block spans lanes 2j, 2j+1
+    const int ex = e4m3_block_exp(amax);
+    const float s = __uint_as_float((uint32_t)(127 + ex) << 23);  // 2^ex, ex >= -120
+    uint8_t q[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) q[e] = e4m3_rne(x[e] * s);
+    uint8_t* o = reinterpret_cast<uint8_t*>(out) + gr * k_out + gk;
+    if (full && vec_out) {
+      i32x4 v;
+#pragma unroll
+      for (int w = 0; w < 4; w++)
+        v[w] = (int)((uint32_t)q[4 * w] | ((uint32_t)q[4 * w + 1] << 8) |
+                     ((uint32_t)q[4 * w + 2] << 16) | ((uint32_t)q[4 * w + 3] << 24));
+      *reinterpret_cast<i32x4*>(o) = v;
+    } else {
+      for (int e = 0; e < 16; e++)
+        if (gk + e < k_out) o[e] = q[e];
+    }
+    if ((kc & 31) == 0 && gk < k_out) {
+      uint8_t* sp = reinterpret_cast<uint8_t*>(out) + rows_out * k_out;
+      sp[gr * (k_out / 32) + gk / 32] = (uint8_t)(127 - ex);
+    }
+    return;
+  }
+
+  constexpr int PARTS = MODE == RISE_MODE_BF16 ? 1 : MODE == RISE_MODE_BF16X3 ? 2 : 3;
+  const int64_t plane = rows_out * k_out;
+#pragma unroll
+  for (int p = 0; p < PARTS; p++) {
+    uint16_t h[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+      h[e] = bf16_rne(x[e]);
+      x[e] = x[e] - bf16_to_f32(h[e]);  // exact residual
+    }
+    uint16_t* o = reinterpret_cast<uint16_t*>(out) + p * plane + gr * k_out + gk;
+    if (full && vec_out) {
+      i32x4 v0, v1;
+#pragma unroll
+      for (int w = 0; w < 4; w++) {
+        v0[w] = (int)((uint32_t)h[2 * w] | ((uint32_t)h[2 * w + 1] << 16));
+        v1[w] = (int)((uint32_t)h[8 + 2 * w] | ((uint32_t)h[8 + 2 * w + 1] << 16));
+      }
+      reinterpret_cast<i32x4*>(o)[0] = v0;
+      reinterpret_cast<i32x4*>(o)[1] = v1;
+    } else {
+      for (int e = 0; e < 16; e++)
+        if (gk + e < k_out) o[e] = h[e];
+    }
+  }
+}
+
+template <typename SRC, int MODE>
+rise_status launch_mode(const PrepArgs& a, hipStream_t s) {
+  dim3 grid((unsigned)((a.rows_out + TR - 1) / TR), (unsigned)((a.k_out + TK - 1) / TK));
+  dim3 block(kThreads);
+  auto aligned = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  int elem_out = MODE == RISE_MODE_FP8 ? 1 : 2;
+  int vec_out = aligned(a.out) && (a.k_out * elem_out) % 16 == 0;
+  const SRC* src = reinterpret_cast<const SRC*>(a.src);
+  int layout = 0;
+  if (sizeof(SRC) == 4 && aligned(a.src)) {
+    if (a.ld_k == 1 && a.ld_r % 4 == 0) layout = 1;
+    else if (a.ld_r == 1 && a.ld_k % 4 == 0) layout = 2;
+  }
+  if (layout == 1)
+    hipLaunchKernelGGL((prep_kernel<SRC, MODE, 1>), grid, block, 0, s, a.out, a.rows_out, a.k_out,
+                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out);
+  else if (layout == 2)
+    hipLaunchKernelGGL((prep_kernel<SRC, MODE, 2>), grid, block, 0, s, a.out, a.rows_out, a.k_out,
+                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out);
+  else
+    hipLaunchKernelGGL((prep_kernel<SRC, MODE, 0>), grid, block, 0, s, a.out, a.rows_out, a.k_out,
+                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out);
+  return check_launch("prep_kernel");
+}
+
+}  // namespace
+
+int prep_parts(rise_mode mode) {
+  switch (mode) {
+    case RISE_MODE_BF16: return 1;
+    case RISE_MODE_BF16X3: return 2;
+    case RISE_MODE_BF16X6: return 3;
+    case RISE_MODE_FP8: return 1;
+    default: return 0;
+  }
+}
+
+size_t prep_bytes(int64_t rows_out, int64_t k_out, rise_mode mode) {
+  if (mode == RISE_MODE_FP8) return (size_t)(rows_out * k_out + rows_out * (k_out / 32));
+  return (size_t)prep_parts(mode) * (size_t)(rows_out * k_out) * 2;
+}
+
+rise_status launch_prep(const PrepArgs& a, hipStream_t s) {
+  if (a.rows_out == 0 || a.k_out == 0) return RISE_OK;
+  if (a.src_bf16) {
+    if (a.mode != RISE_MODE_BF16) return fail(RISE_ERR_DTYPE, "prep: bf16 source needs mode BF16");
+    return launch_mode<uint16_t, RISE_MODE_BF16>(a, s);
+  }
+  switch (a.mode) {
+    case RISE_MODE_BF16: return launch_mode<float, RISE_MODE_BF16>(a, s);
+    case RISE_MODE_BF16X3: return launch_mode<float, RISE_MODE_BF16X3>(a, s);
+    case RISE_MODE_BF16X6: return launch_mode<float, RISE_MODE_BF16X6>(a, s);
+    case RISE_MODE_FP8: return launch_mode<float, RISE_MODE_FP8>(a, s);
+    default: return fail(RISE_ERR_UNSUPPORTED, "prep: mode has no preparation");
+  }
+}
+
+}  // namespace rise

@@ -1,0 +1,132 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and rejects invalid arguments before touching the device (every call
+below returns from host-side validation; none launches a kernel)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rise.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rise_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2201_03611_amd import _lib
+
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "rise_gemm" in names and "rise_stencil2d" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_declares_every_header_function():
+    from paper_2201_03611_amd import _lib
+
+    assert set(declared_functions()) <= set(_lib.exported_names())
+
+
+FAKE_A = 0x10000000
+FAKE_B = 0x20000000
+FAKE_C = 0x30000000
+FAKE_W = 0x40000000
+
+
+def gemm(lib, C=FAKE_C, ldc=64, A=FAKE_A, tA=0, lda=64, opA=0, B=FAKE_B, tB=0, ldb=64, opB=0,
+         M=64, N=64, K=64, mode=0, tile=None, ws=None, ws_bytes=0):
+    return lib.rise_gemm(C, ldc, A, tA, lda, opA, B, tB, ldb, opB, M, N, K, mode, tile, ws,
+                         ws_bytes, None)
+
+
+def test_gemm_rejections(lib):
+    from paper_2201_03611_amd._lib import RiseTile
+
+    assert gemm(lib, C=None) == 1                       # NULL
+    assert gemm(lib, A=None) == 1
+    assert gemm(lib, M=-1) == 2                         # SHAPE
+    assert gemm(lib, M=1 << 31) == 2
+    assert gemm(lib, ldc=63) == 2
+    assert gemm(lib, lda=63) == 2
+    assert gemm(lib, opA=1, lda=63) == 2                # stored K x M needs lda >= M
+    assert gemm(lib, C=FAKE_A + 256) == 3               # ALIAS: C inside A
+    assert gemm(lib, tA=1) == 4                         # DTYPE: F32 mode with bf16 A
+    assert gemm(lib, tA=1, mode=2) == 4                 # split mode needs f32 operands
+    assert gemm(lib, opA=2) == 5                        # UNSUPPORTED
+    assert gemm(lib, mode=9) == 5
+    assert gemm(lib, tile=ctypes.byref(RiseTile(96, 96, 32))) == 5
+    assert gemm(lib, mode=1) == 6                       # WORKSPACE missing
+    need = lib.rise_gemm_workspace(64, 64, 64, 1, None)
+    assert need > 0
+    assert gemm(lib, mode=1, ws=0x50000000, ws_bytes=need - 1) == 6
+    assert gemm(lib, mode=1, ws=0x50000001, ws_bytes=need) == 6  # alignment
+    assert gemm(lib, mode=1, ws=FAKE_A, ws_bytes=need) == 3      # workspace overlaps A
+    assert lib.rise_last_error() != b""
+
+
+def test_gemm_degenerate_sizes_are_noops(lib):
+    assert gemm(lib, M=0) == 0
+    assert gemm(lib, N=0, C=None) == 0
+    assert lib.rise_gemm_workspace(0, 0, 0, 0, None) == 0
+
+
+def test_tiles_and_workspace_queries(lib):
+    from paper_2201_03611_amd._lib import RiseTile
+
+    for mode in range(5):
+        n = lib.rise_gemm_tiles(mode, None, 0)
+        assert n >= 2
+        arr = (RiseTile * n)()
+        assert lib.rise_gemm_tiles(mode, arr, n) == n
+        for t in arr:
+            assert t.bm > 0 and t.bn > 0 and t.bk > 0
+    assert lib.rise_gemm_workspace(4096, 4096, 4096, 0, None) == 0
+    # bf16 hi/lo: two bf16 planes per operand
+    ws3 = lib.rise_gemm_workspace(256, 256, 256, 2, None)
+    assert ws3 >= 2 * 2 * 256 * 256 * 2
+    assert lib.rise_prep_bytes(64, 64, 4) == 64 * 64 + 64 * 2
+    assert lib.rise_prep_bytes(64, 64, 3) == 3 * 64 * 64 * 2
+
+
+def stencil(lib, out=FAKE_C, ld_out=100, inp=FAKE_A, ld_in=100, H=50, W=100, w=FAKE_W, kh=5,
+            kw=5, pad=0):
+    return lib.rise_stencil2d(out, ld_out, inp, ld_in, H, W, w, kh, kw, pad, None)
+
+
+def test_stencil_rejections(lib):
+    assert stencil(lib, out=None) == 1
+    assert stencil(lib, w=None) == 1
+    assert stencil(lib, kh=4) == 5
+    assert stencil(lib, kw=17) == 5
+    assert stencil(lib, kh=0) == 5
+    assert stencil(lib, pad=7) == 5
+    assert stencil(lib, ld_in=99) == 2
+    assert stencil(lib, H=-3) == 2
+    assert stencil(lib, out=FAKE_A + 400) == 3
+    assert stencil(lib, w=FAKE_C + 4) == 3
+    assert stencil(lib, H=0) == 0
+    assert stencil(lib, W=0, out=None) == 0
+
+
+def test_prep_rejections(lib):
+    P = lib.rise_prep_operand
+    assert P(FAKE_C, 64, 64, FAKE_A, 64, 64, 64, 1, 0, None) == 5   # F32 has no preparation
+    assert P(FAKE_C, 32, 64, FAKE_A, 64, 64, 64, 1, 1, None) == 2   # rows_out < rows
+    assert P(FAKE_C, 64, 48, FAKE_A, 64, 40, 64, 1, 4, None) == 2   # FP8 needs k_out % 32 == 0
+    assert P(None, 64, 64, FAKE_A, 64, 64, 64, 1, 1, None) == 1
+    assert P(FAKE_A + 64, 64, 64, FAKE_A, 64, 64, 64, 1, 1, None) == 3
+
+
+def test_status_strings(lib):
+    for s in range(8):
+        assert lib.rise_status_string(s)

@@ -1,0 +1,94 @@
+"""GPU parity of rise_stencil2d against the oracle.
+
+Bar: |out_hat - out| <= 1e-5 * sum |w| |window| per output (the componentwise
+FP32 tolerance); dyadic inputs whose sums are exact in FP32, bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import rise_inputs as ri
+from _helpers import componentwise, dev, host, stencil_scale
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+PADS = {"clamp": oracle.PAD_CLAMP, "zero": oracle.PAD_ZERO}
+
+
+@pytest.fixture(scope="module")
+def rise():
+    import paper_2201_03611_amd as rise
+
+    return rise
+
+
+def run(rise, img, w, pad):
+    print(f"stencil img{img.shape} w{w.shape} pad={pad}", flush=True)
+    return host(rise.stencil2d(dev(img), dev(w), pad=pad))
+
+
+@pytest.mark.parametrize("pad", list(PADS))
+@pytest.mark.parametrize("H,W", [(1, 1), (3, 5), (32, 256), (33, 257), (70, 300), (100, 13),
+                                 (64, 1024)])
+@pytest.mark.parametrize("k", [1, 3, 5, 7])
+def test_tiled_kernel_vs_oracle(rise, pad, H, W, k):
+    g = ri.rng(H * 1000 + W + k)
+    img = ri.uniform_matrix(g, H, W, 0.0, 1.0)
+    w = ri.uniform_matrix(g, k, k)  # asymmetric, signed: catches flips and sign errors
+    out = run(rise, img, w, pad)
+    ref = oracle.stencil2d(img, w, PADS[pad])
+    assert componentwise(out, ref, stencil_scale(img, w, PADS[pad])) <= TOL_F32
+
+
+@pytest.mark.parametrize("kh,kw", [(9, 9), (3, 7), (15, 1), (11, 5)])
+@pytest.mark.parametrize("pad", list(PADS))
+def test_direct_kernel_vs_oracle(rise, kh, kw, pad):
+    g = ri.rng(kh * 17 + kw)
+    img = ri.uniform_matrix(g, 45, 77, 0.0, 1.0)
+    w = ri.uniform_matrix(g, kh, kw)
+    out = run(rise, img, w, pad)
+    ref = oracle.stencil2d(img, w, PADS[pad])
+    assert componentwise(out, ref, stencil_scale(img, w, PADS[pad])) <= TOL_F32
+
+
+@pytest.mark.parametrize("k", [3, 5, 7])
+def test_dyadic_inputs_bit_exact(rise, k):
+    g = ri.rng(k)
+    img = g.integers(0, 16, size=(97, 390)).astype(np.float32)
+    w = (g.integers(-8, 9, size=(k, k)) / 64.0).astype(np.float32)
+    for pad in PADS:
+        out = run(rise, img, w, pad)
+        assert np.array_equal(out, oracle.stencil2d(img, w, PADS[pad]).astype(np.float32))
+
+
+def test_constant_image_binomial_closed_form(rise):
+    b = np.array([1, 4, 6, 4, 1], dtype=np.float64)
+    w = (np.outer(b, b) / 256.0).astype(np.float32)
+    img = np.full((64, 300), 0.625, dtype=np.float32)
+    assert np.array_equal(run(rise, img, w, "clamp"), img)
+
+
+def test_unaligned_leading_dimension(rise):
+    import torch
+
+    g = ri.rng(11)
+    H, W = 50, 121
+    big = ri.uniform_matrix(g, H, W + 1, 0.0, 1.0)
+    w = ri.gaussian_weights(5)
+    out = torch.empty((H, W + 3), device="cuda")
+    rise.rise_stencil2d(out, dev(big), dev(w), H, W, ld_out=W + 3, ld_in=W + 1, kh=5, kw=5)
+    img = np.ascontiguousarray(big[:, :W])
+    ref = oracle.stencil2d(img, w, oracle.PAD_CLAMP)
+    assert componentwise(host(out)[:, :W], ref, stencil_scale(img, w, 0)) <= TOL_F32
+
+
+def test_config_4096_gaussian_full(rise):
+    # the timed stencil workload: 4096 x 4096 U[0,1), 5 x 5 Gaussian sigma = 1, clamp
+    img = ri.image_uniform(4096, 4096, ri.SEED_STENCIL)
+    w = ri.gaussian_weights(5, 1.0)
+    out = run(rise, img, w, "clamp")
+    ref = oracle.stencil2d(img, w, oracle.PAD_CLAMP)
+    err = componentwise(out, ref, stencil_scale(img, w, oracle.PAD_CLAMP))
+    print("4096^2 stencil componentwise max err", err)
+    assert err <= TOL_F32
