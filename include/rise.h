@@ -136,16 +136,37 @@ rise_status rise_prep_operand(void* out, int64_t rows_out, int64_t k_out, const 
 /* 2D stencil                                                               */
 /* ------------------------------------------------------------------------ */
 
+/* How the stencil is scheduled (the choice the paper leaves to an explicit
+ * strategy, Sec. IV-B/C; both schedules compute the same sums in the same order):
+ *  RISE_STENCIL_LDS_TILE: each workgroup stages a halo tile of `rows` output
+ *    rows x 256 columns in LDS (toMem(Local), Sec. V-B), then each lane reduces
+ *    4 adjacent outputs per row from it;
+ *  RISE_STENCIL_STREAM: each wavefront walks down a 256-column strip segment of
+ *    `rows` output rows, keeps the window rows in registers and receives its
+ *    neighbours' columns through wavefront shifts.
+ * rise_stencil_schedules() lists the supported (variant, rows) pairs. */
+typedef enum { RISE_STENCIL_LDS_TILE = 0, RISE_STENCIL_STREAM = 1 } rise_stencil_variant;
+typedef struct {
+  int32_t variant; /* rise_stencil_variant */
+  int32_t rows;
+} rise_stencil_schedule;
+
+/* Number of supported schedules; up to `cap` are written to `out` if non-NULL.
+ * Host-only. */
+int32_t rise_stencil_schedules(rise_stencil_schedule* out, int32_t cap);
+
 /* out = in |> pad2D(pad) |> slide2D(kh x kw, 1)
  *          |> map(map(win => zip(join(win), join(w)) |> map(*) |> reduce(+, 0)))
  * in: H x W FP32 (ld_in), out: H x W FP32 (ld_out), w: kh x kw FP32 weights,
  * row-major, device memory.  Window element (dy, dx) of output (y, x) is
  * input (y + dy - (kh-1)/2, x + dx - (kw-1)/2) (cross-correlation), outside
- * the image either the nearest edge element (clamp) or 0 (zero).
- * kh and kw must be odd and at most 15.  H = 0 or W = 0 is a no-op. */
+ * the image either the nearest edge element (clamp) or 0 (zero).  kh and kw
+ * must be odd and at most 15; square 1, 3, 5 and 7 windows run the scheduled
+ * kernels, other sizes a direct per-output kernel that ignores `sched`.
+ * sched = NULL takes the library default.  H = 0 or W = 0 is a no-op. */
 rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t ld_in,
                            int64_t H, int64_t W, const float* w, int32_t kh, int32_t kw,
-                           rise_pad pad, void* stream);
+                           rise_pad pad, const rise_stencil_schedule* sched, void* stream);
 
 #ifdef __cplusplus
 }

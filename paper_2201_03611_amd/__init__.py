@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import (RISE_BF16, RISE_F32, RISE_MODE_BF16, RISE_MODE_BF16X3, RISE_MODE_BF16X6,
                    RISE_MODE_F32, RISE_MODE_FP8, RISE_OP_N, RISE_OP_T, RISE_PAD_CLAMP,
-                   RISE_PAD_ZERO, RiseTile)
+                   RISE_PAD_ZERO, RISE_STENCIL_LDS_TILE, RISE_STENCIL_STREAM, RiseStencilSchedule,
+                   RiseTile)
 
 lib = _lib.load()
 
@@ -105,11 +106,30 @@ def rise_prep_operand(out, rows_out, k_out, src, rows, K, ld_r, ld_k, mode, stre
     _check(st, "rise_prep_operand")
 
 
-def rise_stencil2d(out, inp, w, H, W, *, ld_out, ld_in, kh, kw, pad="clamp", stream=None):
+SCHEDULES = {"lds": RISE_STENCIL_LDS_TILE, "stream": RISE_STENCIL_STREAM}
+
+
+def rise_stencil_schedules():
+    n = lib.rise_stencil_schedules(None, 0)
+    arr = (RiseStencilSchedule * max(n, 1))()
+    lib.rise_stencil_schedules(arr, n)
+    names = {v: k for k, v in SCHEDULES.items()}
+    return [(names[arr[i].variant], arr[i].rows) for i in range(n)]
+
+
+def _sched(sc):
+    if sc is None:
+        return None
+    v, rows = sc
+    return ctypes.byref(RiseStencilSchedule(SCHEDULES[v] if isinstance(v, str) else int(v), rows))
+
+
+def rise_stencil2d(out, inp, w, H, W, *, ld_out, ld_in, kh, kw, pad="clamp", schedule=None,
+                   stream=None):
     _require_cuda(out, inp, w)
     p = PADS[pad] if isinstance(pad, str) else int(pad)
     st = lib.rise_stencil2d(_ptr(out), ld_out, _ptr(inp), ld_in, H, W, _ptr(w), kh, kw, p,
-                            _stream(stream))
+                            _sched(schedule), _stream(stream))
     _check(st, "rise_stencil2d")
 
 
@@ -136,7 +156,7 @@ def gemm(A, B, *, transA=False, transB=False, mode="f32", tile=None, out=None, w
     return out
 
 
-def stencil2d(img, w, pad="clamp", out=None, stream=None):
+def stencil2d(img, w, pad="clamp", out=None, schedule=None, stream=None):
     img = img.contiguous()
     w = w.contiguous().to(device=img.device, dtype=torch.float32)
     H, W = img.shape
@@ -144,7 +164,7 @@ def stencil2d(img, w, pad="clamp", out=None, stream=None):
     if out is None:
         out = torch.empty((H, W), device=img.device, dtype=torch.float32)
     rise_stencil2d(out, img, w, H, W, ld_out=out.stride(0), ld_in=img.stride(0), kh=kh, kw=kw,
-                   pad=pad, stream=stream)
+                   pad=pad, schedule=schedule, stream=stream)
     return out
 
 

@@ -20,8 +20,15 @@ RISE_OP_N, RISE_OP_T = 0, 1
 RISE_PAD_CLAMP, RISE_PAD_ZERO = 0, 1
 
 
+RISE_STENCIL_LDS_TILE, RISE_STENCIL_STREAM = 0, 1
+
+
 class RiseTile(ctypes.Structure):
     _fields_ = [("bm", ctypes.c_int32), ("bn", ctypes.c_int32), ("bk", ctypes.c_int32)]
+
+
+class RiseStencilSchedule(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -40,7 +47,9 @@ SIGNATURES = {
                          _INT, ctypes.POINTER(RiseTile), _P, _SZ, _P]),
     "rise_prep_bytes": (_SZ, [_I64, _I64, _INT]),
     "rise_prep_operand": (_INT, [_P, _I64, _I64, _P, _I64, _I64, _I64, _I64, _INT, _P]),
-    "rise_stencil2d": (_INT, [_P, _I64, _P, _I64, _I64, _I64, _P, _I32, _I32, _INT, _P]),
+    "rise_stencil_schedules": (_I32, [ctypes.POINTER(RiseStencilSchedule), _I32]),
+    "rise_stencil2d": (_INT, [_P, _I64, _P, _I64, _I64, _I64, _P, _I32, _I32, _INT,
+                              ctypes.POINTER(RiseStencilSchedule), _P]),
 }
 
 

@@ -178,9 +178,13 @@ rise_status rise_prep_operand(void* out, int64_t rows_out, int64_t k_out, const 
   return launch_prep(a, (hipStream_t)stream);
 }
 
+int32_t rise_stencil_schedules(rise_stencil_schedule* out, int32_t cap) {
+  return stencil_schedules(out, cap);
+}
+
 rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t ld_in,
                            int64_t H, int64_t W, const float* w, int32_t kh, int32_t kw,
-                           rise_pad pad, void* stream) {
+                           rise_pad pad, const rise_stencil_schedule* sched, void* stream) {
   clear_error();
   if (!dim_ok(H) || !dim_ok(W) || H * W >= kDimLimit * 2)
     return fail(RISE_ERR_SHAPE, "rise_stencil2d: sizes must be in [0, 2^31)");
@@ -194,8 +198,11 @@ rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t 
   Range ro = span(out, H, W, ld_out, 4);
   if (overlaps(ro, span(in, H, W, ld_in, 4)) || overlaps(ro, span(w, kh, kw, kw, 4)))
     return fail(RISE_ERR_ALIAS, "rise_stencil2d: out overlaps in or w");
+  rise_stencil_schedule sc = sched ? *sched : stencil_default_schedule((int)H, (int)W, kh, kw);
+  if (!stencil_schedule_supported(sc))
+    return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d: unknown schedule");
   StencilArgs a{out, ld_out, in, ld_in, (int)H, (int)W, w, kh, kw, (int)pad};
-  return launch_stencil2d(a, (hipStream_t)stream);
+  return launch_stencil2d(a, sc, (hipStream_t)stream);
 }
 
 }  // extern "C"

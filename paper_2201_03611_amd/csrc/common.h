@@ -78,6 +78,9 @@ struct StencilArgs {
   int kh, kw;
   int pad;  // rise_pad
 };
-rise_status launch_stencil2d(const StencilArgs& a, hipStream_t s);
+int stencil_schedules(rise_stencil_schedule* out, int cap);
+bool stencil_schedule_supported(const rise_stencil_schedule& sc);
+rise_stencil_schedule stencil_default_schedule(int H, int W, int kh, int kw);
+rise_status launch_stencil2d(const StencilArgs& a, const rise_stencil_schedule& sc, hipStream_t s);
 
 }  // namespace rise

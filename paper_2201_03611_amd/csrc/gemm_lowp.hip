@@ -241,23 +241,25 @@ __global__ __launch_bounds__(kThreads, 1) void packed_fp8_kernel(
     if (more) fetch((kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 64; ks++) {
-      // lane supplies 32 consecutive k: slab bytes 64*ks + 32*kh .. +31 (2 chunks),
-      // which form scale block 2*ks + kh of its row
-      const int c0 = 4 * ks + 2 * kh;
+      // Operand registers 0-3 of both lane halves form scale block 2*ks (the
+      // scale comes from the lane in half 0), registers 4-7 form block 2*ks+1
+      // (scale from half 1).  So half kh takes 16-byte chunk kh of each of the
+      // two 32-byte blocks, and supplies the scale of block 2*ks + kh.
+      const int c0 = 4 * ks + kh, c1 = 4 * ks + 2 + kh;
       const int sh = 8 * (2 * ks + kh);
       i32x8 a[TM], b[TN];
       int xa[TM], xb[TN];
 #pragma unroll
       for (int i = 0; i < TM; i++) {
         const int r = wm0 + 32 * i + il;
-        i32x4 lo = As[cur][swz<CH>(r, c0)], hi = As[cur][swz<CH>(r, c0 + 1)];
+        i32x4 lo = As[cur][swz<CH>(r, c0)], hi = As[cur][swz<CH>(r, c1)];
         a[i] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         xa[i] = (int)((Asc[cur][r] >> sh) & 0xffu);
       }
 #pragma unroll
       for (int j = 0; j < TN; j++) {
         const int r = wn0 + 32 * j + il;
-        i32x4 lo = Bs[cur][swz<CH>(r, c0)], hi = Bs[cur][swz<CH>(r, c0 + 1)];
+        i32x4 lo = Bs[cur][swz<CH>(r, c0)], hi = Bs[cur][swz<CH>(r, c1)];
         b[j] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         xb[j] = (int)((Bsc[cur][r] >> sh) & 0xffu);
       }

@@ -15,28 +15,30 @@
 //   zip |> map(*) |> reduce -> k*k FMAs per output in registers (fuseReduceMap,
 //                             Sec. IV-B), weights in scalar registers;
 //   join                   -> 16-byte coalesced stores.
-// Square windows of 1, 3, 5 and 7 use this kernel; other odd sizes up to 15
-// use a direct per-output kernel.
+// That is the LDS halo-tile schedule.  The streaming schedule below keeps the
+// window in registers instead and exchanges neighbours with wavefront shifts;
+// the caller picks one through rise_stencil_schedule (both compute the same
+// sums in the same order).  Square windows of 1, 3, 5 and 7 use these
+// kernels; other odd sizes up to 15 use a direct per-output kernel.
 #include "common.h"
 
 namespace rise {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int TX = 256;            // columns per workgroup (64 lanes x 4)
-constexpr int TY = 32;             // rows per workgroup (4 waves x 8)
-constexpr int RW = TY / 4;         // rows per wave
+constexpr int TX = 256;            // columns per workgroup / wave strip (64 lanes x 4)
 constexpr int HALO = 4;            // LDS columns left and right of the tile
 constexpr int LCOLS = TX + 2 * HALO;
 constexpr int LCHUNKS = LCOLS / 4;  // 16-byte chunks per LDS row
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-template <int K, bool VEC>
+template <int K, bool VEC, int TY>
 __global__ __launch_bounds__(kThreads) void stencil2d_tiled(
     float* __restrict__ out, int64_t ld_out, const float* __restrict__ in, int64_t ld_in, int H,
     int W, const float* __restrict__ w, int zero_pad, int tiles_x) {
   constexpr int R = (K - 1) / 2;
+  constexpr int RW = TY / 4;  // output rows per wave
   constexpr int ROWS = TY + 2 * R;
   constexpr int TOTAL = ROWS * LCHUNKS;
   constexpr int PER = (TOTAL + kThreads - 1) / kThreads;
@@ -143,6 +145,131 @@ __global__ __launch_bounds__(kThreads) void stencil2d_tiled(
   }
 }
 
+// Streaming schedule: every wave owns one 256-column strip segment of `L`
+// output rows and walks down it.  Each input row of the segment (plus the r
+// halo rows above and below) is fetched once as one 16-byte chunk per lane;
+// the chunks of the neighbouring lanes (columns x-4..x-1 and x+4..x+7) arrive
+// through wavefront shifts (DPP wave_shr / wave_shl), and only lanes 0 and 63
+// fetch the 4 columns beyond the strip.  Input rows are prefetched P rows
+// ahead into registers; the k window rows live in a register ring.  No LDS and
+// no barriers: waves run independently, so loads and FMAs of different waves
+// overlap freely.
+__device__ __forceinline__ float wave_from_left(float v) {  // lane l receives lane l-1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_from_right(float v) {  // lane l receives lane l+1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+template <bool VEC>
+__device__ __forceinline__ f32x4 load_chunk4(const float* __restrict__ in, int64_t ld_in, int H,
+                                             int W, int gy, int gx, int zero_pad) {
+  // 4 consecutive elements of padded row gy starting at padded column gx
+  if (gy < 0 || gy >= H) {
+    if (zero_pad) return f32x4{0.f, 0.f, 0.f, 0.f};
+    gy = clampi(gy, 0, H - 1);
+  }
+  const float* rp = in + (int64_t)gy * ld_in;
+  if (VEC && gx >= 0 && gx + 3 < W) return *reinterpret_cast<const f32x4*>(rp + gx);
+  float e[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    int xx = gx + q;
+    if (xx < 0 || xx >= W)
+      e[q] = zero_pad ? 0.f : rp[clampi(xx, 0, W - 1)];
+    else
+      e[q] = rp[xx];
+  }
+  return f32x4{e[0], e[1], e[2], e[3]};
+}
+
+template <int K, bool VEC, int L>
+__global__ __launch_bounds__(kThreads) void stencil2d_stream(
+    float* __restrict__ out, int64_t ld_out, const float* __restrict__ in, int64_t ld_in, int H,
+    int W, const float* __restrict__ w, int zero_pad, int segs, int tasks) {
+  constexpr int R = (K - 1) / 2;
+  constexpr int P = K >= 4 ? K : K * ((4 + K - 1) / K);  // prefetch depth, a multiple of K
+  constexpr int NIN = L + 2 * R;                          // input rows consumed per segment
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int task = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
+  if (task >= tasks) return;  // whole wave leaves; no barriers in this kernel
+  const int strip = task / segs, seg = task - strip * segs;
+  const int x0 = strip * TX, x = x0 + 4 * lane;
+  const int ys = seg * L;
+  const int edge_x = lane == 0 ? x0 - 4 : x0 + TX;  // used by lanes 0 and 63 only
+  const bool edge_lane = lane == 0 || lane == 63;
+
+  float wt[K][K];
+#pragma unroll
+  for (int dy = 0; dy < K; dy++)
+#pragma unroll
+    for (int dx = 0; dx < K; dx++) wt[dy][dx] = w[dy * K + dx];
+
+  f32x4 raw[P], edge[P];
+  float win[K][12];
+#pragma unroll
+  for (int p = 0; p < P; p++) edge[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto fetch = [&](int t, int slot) {  // input row t of the segment = padded row ys - R + t
+    const int gy = ys - R + t;
+    raw[slot] = load_chunk4<VEC>(in, ld_in, H, W, gy, x, zero_pad);
+    if (edge_lane) edge[slot] = load_chunk4<VEC>(in, ld_in, H, W, gy, edge_x, zero_pad);
+  };
+
+#pragma unroll
+  for (int p = 0; p < P; p++)
+    if (p < NIN) fetch(p, p);
+
+  for (int t0 = 0; t0 < NIN; t0 += P) {
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      const int t = t0 + p;
+      if (t >= NIN) break;
+      // expand input row t into its window slot: [x-4..x-1 | x..x+3 | x+4..x+7]
+      float* row = win[p % K];
+      const f32x4 c = raw[p];
+      const f32x4 e = edge[p];
+      row[4] = c.x; row[5] = c.y; row[6] = c.z; row[7] = c.w;
+      if (R > 0) {
+        float l0 = wave_from_left(c.x), l1 = wave_from_left(c.y);
+        float l2 = wave_from_left(c.z), l3 = wave_from_left(c.w);
+        float r0 = wave_from_right(c.x), r1 = wave_from_right(c.y);
+        float r2 = wave_from_right(c.z), r3 = wave_from_right(c.w);
+        if (lane == 0) { l0 = e.x; l1 = e.y; l2 = e.z; l3 = e.w; }
+        if (lane == 63) { r0 = e.x; r1 = e.y; r2 = e.z; r3 = e.w; }
+        row[0] = l0; row[1] = l1; row[2] = l2; row[3] = l3;
+        row[8] = r0; row[9] = r1; row[10] = r2; row[11] = r3;
+      }
+      if (t + P < NIN) fetch(t + P, p);
+      if (t >= 2 * R) {
+        const int y = ys + t - 2 * R;
+        if (y < H) {
+          float acc[4];
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            float a = 0.f;
+#pragma unroll
+            for (int dy = 0; dy < K; dy++)
+#pragma unroll
+              for (int dx = 0; dx < K; dx++)
+                a = fmaf(win[(p + K - 2 * R + dy) % K][4 + q + dx - R], wt[dy][dx], a);
+            acc[q] = a;
+          }
+          float* op = out + (int64_t)y * ld_out;
+          if (VEC && x + 3 < W) {
+            *reinterpret_cast<f32x4*>(op + x) = f32x4{acc[0], acc[1], acc[2], acc[3]};
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+              if (x + q < W) op[x + q] = acc[q];
+          }
+        }
+      }
+    }
+  }
+}
+
 // Any odd kh x kw up to 15 x 15: one thread per output, reads through the
 // caches with clamped or zero-filled indices.
 __global__ __launch_bounds__(kThreads) void stencil2d_direct(
@@ -169,31 +296,71 @@ __global__ __launch_bounds__(kThreads) void stencil2d_direct(
   out[(int64_t)y * ld_out + x] = a;
 }
 
-template <int K>
-rise_status launch_tiled(const StencilArgs& a, bool vec, hipStream_t s) {
+template <int K, bool VEC, int TY>
+rise_status launch_tiled(const StencilArgs& a, hipStream_t s) {
   int tiles_x = (a.W + TX - 1) / TX, tiles_y = (a.H + TY - 1) / TY;
-  dim3 grid(tiles_x * tiles_y), block(kThreads);
-  int zero = a.pad == RISE_PAD_ZERO;
-  if (vec)
-    hipLaunchKernelGGL((stencil2d_tiled<K, true>), grid, block, 0, s, a.out, a.ld_out, a.in,
-                       a.ld_in, a.H, a.W, a.w, zero, tiles_x);
-  else
-    hipLaunchKernelGGL((stencil2d_tiled<K, false>), grid, block, 0, s, a.out, a.ld_out, a.in,
-                       a.ld_in, a.H, a.W, a.w, zero, tiles_x);
+  hipLaunchKernelGGL((stencil2d_tiled<K, VEC, TY>), dim3(tiles_x * tiles_y), dim3(kThreads), 0, s,
+                     a.out, a.ld_out, a.in, a.ld_in, a.H, a.W, a.w, (int)(a.pad == RISE_PAD_ZERO),
+                     tiles_x);
   return check_launch("stencil2d_tiled");
 }
 
+template <int K, bool VEC, int L>
+rise_status launch_stream(const StencilArgs& a, hipStream_t s) {
+  int strips = (a.W + TX - 1) / TX, segs = (a.H + L - 1) / L;
+  int tasks = strips * segs;
+  hipLaunchKernelGGL((stencil2d_stream<K, VEC, L>), dim3((tasks + 3) / 4), dim3(kThreads), 0, s,
+                     a.out, a.ld_out, a.in, a.ld_in, a.H, a.W, a.w, (int)(a.pad == RISE_PAD_ZERO),
+                     segs, tasks);
+  return check_launch("stencil2d_stream");
+}
+
+template <int K, bool VEC>
+rise_status launch_k(const StencilArgs& a, const rise_stencil_schedule& sc, hipStream_t s) {
+  if (sc.variant == RISE_STENCIL_LDS_TILE) {
+    if (sc.rows == 16) return launch_tiled<K, VEC, 16>(a, s);
+    if (sc.rows == 32) return launch_tiled<K, VEC, 32>(a, s);
+  } else {
+    if (sc.rows == 16) return launch_stream<K, VEC, 16>(a, s);
+    if (sc.rows == 32) return launch_stream<K, VEC, 32>(a, s);
+    if (sc.rows == 64) return launch_stream<K, VEC, 64>(a, s);
+    if (sc.rows == 128) return launch_stream<K, VEC, 128>(a, s);
+  }
+  return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d: schedule rows");
+}
+
+const rise_stencil_schedule kSchedules[] = {
+    {RISE_STENCIL_LDS_TILE, 16}, {RISE_STENCIL_LDS_TILE, 32}, {RISE_STENCIL_STREAM, 16},
+    {RISE_STENCIL_STREAM, 32},   {RISE_STENCIL_STREAM, 64},   {RISE_STENCIL_STREAM, 128}};
+
 }  // namespace
 
-rise_status launch_stencil2d(const StencilArgs& a, hipStream_t s) {
+int stencil_schedules(rise_stencil_schedule* out, int cap) {
+  int n = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
+  for (int i = 0; out && i < n && i < cap; i++) out[i] = kSchedules[i];
+  return n;
+}
+
+bool stencil_schedule_supported(const rise_stencil_schedule& sc) {
+  for (const auto& k : kSchedules)
+    if (k.variant == sc.variant && k.rows == sc.rows) return true;
+  return false;
+}
+
+rise_stencil_schedule stencil_default_schedule(int H, int W, int kh, int kw) {
+  return rise_stencil_schedule{RISE_STENCIL_STREAM, 32};
+}
+
+rise_status launch_stencil2d(const StencilArgs& a, const rise_stencil_schedule& sc,
+                             hipStream_t s) {
   auto aligned = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   bool vec = aligned(a.in) && aligned(a.out) && a.ld_in % 4 == 0 && a.ld_out % 4 == 0;
   if (a.kh == a.kw) {
     switch (a.kh) {
-      case 1: return launch_tiled<1>(a, vec, s);
-      case 3: return launch_tiled<3>(a, vec, s);
-      case 5: return launch_tiled<5>(a, vec, s);
-      case 7: return launch_tiled<7>(a, vec, s);
+      case 1: return vec ? launch_k<1, true>(a, sc, s) : launch_k<1, false>(a, sc, s);
+      case 3: return vec ? launch_k<3, true>(a, sc, s) : launch_k<3, false>(a, sc, s);
+      case 5: return vec ? launch_k<5, true>(a, sc, s) : launch_k<5, false>(a, sc, s);
+      case 7: return vec ? launch_k<7, true>(a, sc, s) : launch_k<7, false>(a, sc, s);
       default: break;
     }
   }

@@ -99,8 +99,8 @@ def test_tiles_and_workspace_queries(lib):
 
 
 def stencil(lib, out=FAKE_C, ld_out=100, inp=FAKE_A, ld_in=100, H=50, W=100, w=FAKE_W, kh=5,
-            kw=5, pad=0):
-    return lib.rise_stencil2d(out, ld_out, inp, ld_in, H, W, w, kh, kw, pad, None)
+            kw=5, pad=0, sched=None):
+    return lib.rise_stencil2d(out, ld_out, inp, ld_in, H, W, w, kh, kw, pad, sched, None)
 
 
 def test_stencil_rejections(lib):
@@ -114,6 +114,11 @@ def test_stencil_rejections(lib):
     assert stencil(lib, H=-3) == 2
     assert stencil(lib, out=FAKE_A + 400) == 3
     assert stencil(lib, w=FAKE_C + 4) == 3
+    from paper_2201_03611_amd._lib import RiseStencilSchedule
+
+    assert stencil(lib, sched=ctypes.byref(RiseStencilSchedule(1, 48))) == 5
+    assert stencil(lib, sched=ctypes.byref(RiseStencilSchedule(7, 32))) == 5
+    assert lib.rise_stencil_schedules(None, 0) >= 2
     assert stencil(lib, H=0) == 0
     assert stencil(lib, W=0, out=None) == 0
 

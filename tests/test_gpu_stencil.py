@@ -23,9 +23,9 @@ def rise():
     return rise
 
 
-def run(rise, img, w, pad):
-    print(f"stencil img{img.shape} w{w.shape} pad={pad}", flush=True)
-    return host(rise.stencil2d(dev(img), dev(w), pad=pad))
+def run(rise, img, w, pad, schedule=None):
+    print(f"stencil img{img.shape} w{w.shape} pad={pad} schedule={schedule}", flush=True)
+    return host(rise.stencil2d(dev(img), dev(w), pad=pad, schedule=schedule))
 
 
 @pytest.mark.parametrize("pad", list(PADS))
@@ -36,9 +36,11 @@ def test_tiled_kernel_vs_oracle(rise, pad, H, W, k):
     g = ri.rng(H * 1000 + W + k)
     img = ri.uniform_matrix(g, H, W, 0.0, 1.0)
     w = ri.uniform_matrix(g, k, k)  # asymmetric, signed: catches flips and sign errors
-    out = run(rise, img, w, pad)
     ref = oracle.stencil2d(img, w, PADS[pad])
-    assert componentwise(out, ref, stencil_scale(img, w, PADS[pad])) <= TOL_F32
+    scale = stencil_scale(img, w, PADS[pad])
+    for sc in rise.rise_stencil_schedules():
+        out = run(rise, img, w, pad, sc)
+        assert componentwise(out, ref, scale) <= TOL_F32, sc
 
 
 @pytest.mark.parametrize("kh,kw", [(9, 9), (3, 7), (15, 1), (11, 5)])
@@ -58,15 +60,17 @@ def test_dyadic_inputs_bit_exact(rise, k):
     img = g.integers(0, 16, size=(97, 390)).astype(np.float32)
     w = (g.integers(-8, 9, size=(k, k)) / 64.0).astype(np.float32)
     for pad in PADS:
-        out = run(rise, img, w, pad)
-        assert np.array_equal(out, oracle.stencil2d(img, w, PADS[pad]).astype(np.float32))
+        ref = oracle.stencil2d(img, w, PADS[pad]).astype(np.float32)
+        for sc in rise.rise_stencil_schedules():
+            assert np.array_equal(run(rise, img, w, pad, sc), ref), (pad, sc)
 
 
 def test_constant_image_binomial_closed_form(rise):
     b = np.array([1, 4, 6, 4, 1], dtype=np.float64)
     w = (np.outer(b, b) / 256.0).astype(np.float32)
     img = np.full((64, 300), 0.625, dtype=np.float32)
-    assert np.array_equal(run(rise, img, w, "clamp"), img)
+    for sc in rise.rise_stencil_schedules():
+        assert np.array_equal(run(rise, img, w, "clamp", sc), img), sc
 
 
 def test_unaligned_leading_dimension(rise):
@@ -76,19 +80,22 @@ def test_unaligned_leading_dimension(rise):
     H, W = 50, 121
     big = ri.uniform_matrix(g, H, W + 1, 0.0, 1.0)
     w = ri.gaussian_weights(5)
-    out = torch.empty((H, W + 3), device="cuda")
-    rise.rise_stencil2d(out, dev(big), dev(w), H, W, ld_out=W + 3, ld_in=W + 1, kh=5, kw=5)
     img = np.ascontiguousarray(big[:, :W])
     ref = oracle.stencil2d(img, w, oracle.PAD_CLAMP)
-    assert componentwise(host(out)[:, :W], ref, stencil_scale(img, w, 0)) <= TOL_F32
+    for sc in rise.rise_stencil_schedules():
+        out = torch.empty((H, W + 3), device="cuda")
+        rise.rise_stencil2d(out, dev(big), dev(w), H, W, ld_out=W + 3, ld_in=W + 1, kh=5, kw=5,
+                            schedule=sc)
+        assert componentwise(host(out)[:, :W], ref, stencil_scale(img, w, 0)) <= TOL_F32, sc
 
 
 def test_config_4096_gaussian_full(rise):
     # the timed stencil workload: 4096 x 4096 U[0,1), 5 x 5 Gaussian sigma = 1, clamp
     img = ri.image_uniform(4096, 4096, ri.SEED_STENCIL)
     w = ri.gaussian_weights(5, 1.0)
-    out = run(rise, img, w, "clamp")
     ref = oracle.stencil2d(img, w, oracle.PAD_CLAMP)
-    err = componentwise(out, ref, stencil_scale(img, w, oracle.PAD_CLAMP))
-    print("4096^2 stencil componentwise max err", err)
-    assert err <= TOL_F32
+    scale = stencil_scale(img, w, oracle.PAD_CLAMP)
+    for sc in [None] + rise.rise_stencil_schedules():
+        err = componentwise(run(rise, img, w, "clamp", sc), ref, scale)
+        print("4096^2 stencil componentwise max err", sc, err)
+        assert err <= TOL_F32, sc
