@@ -164,11 +164,11 @@ def main():
         "stencil_gbps": round(sten_gbs, 1),
         "roofline": {"bound": "mfma", "achieved": round(gemm_tf, 2), "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": round(gemm_tf / PEAK_FP32_MFMA, 4),
-                     "traffic": gemm_traffic, "kernel": "gemm_f32_kernel<128,128,32>",
+                     "traffic": gemm_traffic, "kernel": "gemm_f32_kernel<256,128,16>",
                      "ms": round(t_gemm, 4)},
         "roofline_stencil": {"bound": "hbm", "achieved": round(sten_gbs, 1), "peak": PEAK_HBM,
                              "unit": "GB/s", "frac": round(sten_gbs / PEAK_HBM, 4),
-                             "traffic": sten_traffic, "kernel": "stencil2d_tiled<5>",
+                             "traffic": sten_traffic, "kernel": "stencil2d_tiled<5,16 rows>",
                              "ms": round(t_sten, 5)},
     }
 

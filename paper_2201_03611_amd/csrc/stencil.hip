@@ -348,7 +348,8 @@ bool stencil_schedule_supported(const rise_stencil_schedule& sc) {
 }
 
 rise_stencil_schedule stencil_default_schedule(int H, int W, int kh, int kw) {
-  return rise_stencil_schedule{RISE_STENCIL_STREAM, 32};
+  // measured on 4096^2: the 16-row LDS tile is fastest for 3x3, 5x5 and 7x7
+  return rise_stencil_schedule{RISE_STENCIL_LDS_TILE, 16};
 }
 
 rise_status launch_stencil2d(const StencilArgs& a, const rise_stencil_schedule& sc,
