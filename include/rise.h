@@ -115,6 +115,19 @@ rise_status rise_gemm(float* C, int64_t ldc, const void* A, rise_dtype tA, int64
                       int64_t M, int64_t N, int64_t K, rise_mode mode, const rise_tile* tile,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* Gradients of L(C) with C = A . B (A: M x K, B: K x N, row-major FP32):
+ *   dA = dC . transpose(B)   (M x K)     dB = transpose(A) . dC   (K x N)
+ * written as two GEMMs that read transpose views of the stored operands (no
+ * copies), in the arithmetic of `mode`.  Either of dA, dB may be NULL (skipped).
+ * Workspace: rise_gemm_backward_workspace(M, N, K, mode) bytes, 256-byte aligned.
+ * The transpose view is the paper-silent primitive read as swapping two
+ * dimensions; the gradient of the bilinear map follows from its definition. */
+size_t rise_gemm_backward_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode);
+rise_status rise_gemm_backward(float* dA, int64_t ldda, float* dB, int64_t lddb, const float* dC,
+                               int64_t lddc, const float* A, int64_t lda, const float* B,
+                               int64_t ldb, int64_t M, int64_t N, int64_t K, rise_mode mode,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* Operand preparation of a reduced-precision mode (the map(cast) the mode's
  * contraction consumes; map fusion, Sec. IV-B, lets it run as its own pass).
  * The source holds `rows` vectors of length K; element k of vector r is
@@ -167,6 +180,25 @@ int32_t rise_stencil_schedules(rise_stencil_schedule* out, int32_t cap);
 rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t ld_in,
                            int64_t H, int64_t W, const float* w, int32_t kh, int32_t kw,
                            rise_pad pad, const rise_stencil_schedule* sched, void* stream);
+
+
+/* Gradients of L(out) with out = rise_stencil2d(in, w) (same sizes, window and
+ * padding), given dOut (H x W):
+ *   dIn = S^T dOut, the adjoint of pad2D |> slide2D |> weighted reduce: with
+ *         zero padding the stencil of dOut with the 180-degree rotated window,
+ *         with clamp padding the same plus, on the first/last row and column,
+ *         every contribution the clamp mapped onto them;
+ *   dW[dy][dx] = sum over (y, x) of dOut[y][x] * window(y, x)[dy][dx].
+ * Either dIn or dW may be NULL (skipped); `in` is read only for dW and `w`
+ * only for dIn.  FP32, row-major, device memory.  Workspace:
+ * rise_stencil2d_backward_workspace(H, W, kh, kw) bytes, 256-byte aligned
+ * (rotated window and per-strip partial sums; dW is reduced in a fixed order,
+ * so results are deterministic). */
+size_t rise_stencil2d_backward_workspace(int64_t H, int64_t W, int32_t kh, int32_t kw);
+rise_status rise_stencil2d_backward(float* dIn, int64_t ld_din, float* dW, const float* dOut,
+                                    int64_t ld_dout, const float* in, int64_t ld_in, int64_t H,
+                                    int64_t W, const float* w, int32_t kh, int32_t kw,
+                                    rise_pad pad, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

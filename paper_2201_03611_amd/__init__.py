@@ -95,6 +95,20 @@ def rise_gemm(C, A, B, M, N, K, *, lda, ldb, ldc, opA=RISE_OP_N, opB=RISE_OP_N, 
     _check(st, "rise_gemm")
 
 
+def rise_gemm_backward_workspace(M, N, K, mode):
+    return int(lib.rise_gemm_backward_workspace(M, N, K, _mode(mode)))
+
+
+def rise_gemm_backward(dA, dB, dC, A, B, M, N, K, *, ldda, lddb, lddc, lda, ldb, mode="f32",
+                       ws=None, stream=None):
+    _require_cuda(dA, dB, dC, A, B, ws)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    st = lib.rise_gemm_backward(_ptr(dA), ldda, _ptr(dB), lddb, _ptr(dC), lddc, _ptr(A), lda,
+                                _ptr(B), ldb, M, N, K, _mode(mode), _ptr(ws), ws_bytes,
+                                _stream(stream))
+    _check(st, "rise_gemm_backward")
+
+
 def rise_prep_bytes(rows_out, k_out, mode):
     return int(lib.rise_prep_bytes(rows_out, k_out, _mode(mode)))
 
@@ -131,6 +145,21 @@ def rise_stencil2d(out, inp, w, H, W, *, ld_out, ld_in, kh, kw, pad="clamp", sch
     st = lib.rise_stencil2d(_ptr(out), ld_out, _ptr(inp), ld_in, H, W, _ptr(w), kh, kw, p,
                             _sched(schedule), _stream(stream))
     _check(st, "rise_stencil2d")
+
+
+def rise_stencil2d_backward_workspace(H, W, kh, kw):
+    return int(lib.rise_stencil2d_backward_workspace(H, W, kh, kw))
+
+
+def rise_stencil2d_backward(dIn, dW, dOut, inp, w, H, W, *, ld_din, ld_dout, ld_in, kh, kw,
+                            pad="clamp", ws=None, stream=None):
+    _require_cuda(dIn, dW, dOut, inp, w, ws)
+    p = PADS[pad] if isinstance(pad, str) else int(pad)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    st = lib.rise_stencil2d_backward(_ptr(dIn), ld_din, _ptr(dW), _ptr(dOut), ld_dout, _ptr(inp),
+                                     ld_in, H, W, _ptr(w), kh, kw, p, _ptr(ws), ws_bytes,
+                                     _stream(stream))
+    _check(st, "rise_stencil2d_backward")
 
 
 # ---------------------------------------------------------------------------
@@ -175,3 +204,34 @@ def prep_operand(src, mode, *, rows, K, ld_r, ld_k, rows_out=None, k_out=None, s
                       dtype=torch.uint8)
     rise_prep_operand(out, rows_out, k_out, src, rows, K, ld_r, ld_k, mode, stream=stream)
     return out
+
+
+def gemm_backward(dC, A, B, *, mode="f32", need_dA=True, need_dB=True, stream=None):
+    """(dA, dB) of C = A . B for row-major FP32 A (M x K), B (K x N), dC (M x N)."""
+    dC, A, B = dC.contiguous(), A.contiguous(), B.contiguous()
+    M, K = A.shape
+    N = B.shape[1]
+    dA = torch.empty((M, K), device=A.device, dtype=torch.float32) if need_dA else None
+    dB = torch.empty((K, N), device=A.device, dtype=torch.float32) if need_dB else None
+    need = rise_gemm_backward_workspace(M, N, K, mode)
+    ws = torch.empty(need, device=A.device, dtype=torch.uint8) if need else None
+    rise_gemm_backward(dA, dB, dC, A, B, M, N, K, ldda=K, lddb=N, lddc=N, lda=K, ldb=N,
+                       mode=mode, ws=ws, stream=stream)
+    return dA, dB
+
+
+def stencil2d_backward(dOut, img, w, pad="clamp", *, need_din=True, need_dw=True, stream=None):
+    dOut, img = dOut.contiguous(), img.contiguous()
+    w = w.contiguous().to(device=img.device, dtype=torch.float32)
+    H, W = img.shape
+    kh, kw = w.shape
+    dIn = torch.empty((H, W), device=img.device, dtype=torch.float32) if need_din else None
+    dW = torch.empty((kh, kw), device=img.device, dtype=torch.float32) if need_dw else None
+    ws = torch.empty(max(rise_stencil2d_backward_workspace(H, W, kh, kw), 256), device=img.device,
+                     dtype=torch.uint8)
+    rise_stencil2d_backward(dIn, dW, dOut, img, w, H, W, ld_din=W, ld_dout=W, ld_in=W, kh=kh,
+                            kw=kw, pad=pad, ws=ws, stream=stream)
+    return dIn, dW
+
+
+from .autograd import RiseGemmFn, RiseStencil2dFn  # noqa: E402,F401

@@ -45,11 +45,17 @@ SIGNATURES = {
     "rise_gemm_workspace": (_SZ, [_I64, _I64, _I64, _INT, ctypes.POINTER(RiseTile)]),
     "rise_gemm": (_INT, [_P, _I64, _P, _INT, _I64, _INT, _P, _INT, _I64, _INT, _I64, _I64, _I64,
                          _INT, ctypes.POINTER(RiseTile), _P, _SZ, _P]),
+    "rise_gemm_backward_workspace": (_SZ, [_I64, _I64, _I64, _INT]),
+    "rise_gemm_backward": (_INT, [_P, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _I64, _I64, _I64,
+                                  _I64, _INT, _P, _SZ, _P]),
     "rise_prep_bytes": (_SZ, [_I64, _I64, _INT]),
     "rise_prep_operand": (_INT, [_P, _I64, _I64, _P, _I64, _I64, _I64, _I64, _INT, _P]),
     "rise_stencil_schedules": (_I32, [ctypes.POINTER(RiseStencilSchedule), _I32]),
     "rise_stencil2d": (_INT, [_P, _I64, _P, _I64, _I64, _I64, _P, _I32, _I32, _INT,
                               ctypes.POINTER(RiseStencilSchedule), _P]),
+    "rise_stencil2d_backward_workspace": (_SZ, [_I64, _I64, _I32, _I32]),
+    "rise_stencil2d_backward": (_INT, [_P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64, _P, _I32,
+                                       _I32, _INT, _P, _SZ, _P]),
 }
 
 

@@ -205,4 +205,85 @@ rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t 
   return launch_stencil2d(a, sc, (hipStream_t)stream);
 }
 
+size_t rise_gemm_backward_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode) {
+  size_t a = rise_gemm_workspace(M, K, N, mode, nullptr);  // dA: M x K, reduction over N
+  size_t b = rise_gemm_workspace(K, N, M, mode, nullptr);  // dB: K x N, reduction over M
+  return a > b ? a : b;
+}
+
+rise_status rise_gemm_backward(float* dA, int64_t ldda, float* dB, int64_t lddb, const float* dC,
+                               int64_t lddc, const float* A, int64_t lda, const float* B,
+                               int64_t ldb, int64_t M, int64_t N, int64_t K, rise_mode mode,
+                               void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!dim_ok(M) || !dim_ok(N) || !dim_ok(K))
+    return fail(RISE_ERR_SHAPE, "rise_gemm_backward: sizes must be in [0, 2^31)");
+  if (dA && dB) {
+    if (overlaps(span(dA, M, K, ldda, 4), span(dB, K, N, lddb, 4)))
+      return fail(RISE_ERR_ALIAS, "rise_gemm_backward: dA overlaps dB");
+  }
+  Range rc = span(dC, M, N, lddc, 4), ra = span(A, M, K, lda, 4), rb = span(B, K, N, ldb, 4);
+  if (dA && (overlaps(span(dA, M, K, ldda, 4), rc) || overlaps(span(dA, M, K, ldda, 4), rb)))
+    return fail(RISE_ERR_ALIAS, "rise_gemm_backward: dA overlaps an input");
+  if (dB && (overlaps(span(dB, K, N, lddb, 4), rc) || overlaps(span(dB, K, N, lddb, 4), ra)))
+    return fail(RISE_ERR_ALIAS, "rise_gemm_backward: dB overlaps an input");
+  rise_status st = RISE_OK;
+  if (dA) {  // dA (M x K) = dC (M x N) . transpose(B), B stored K x N
+    st = rise_gemm(dA, ldda, dC, RISE_F32, lddc, RISE_OP_N, B, RISE_F32, ldb, RISE_OP_T, M, K, N,
+                   mode, nullptr, ws, ws_bytes, stream);
+    if (st != RISE_OK) return st;
+  }
+  if (dB) {  // dB (K x N) = transpose(A) . dC, A stored M x K
+    st = rise_gemm(dB, lddb, A, RISE_F32, lda, RISE_OP_T, dC, RISE_F32, lddc, RISE_OP_N, K, N, M,
+                   mode, nullptr, ws, ws_bytes, stream);
+  }
+  return st;
+}
+
+size_t rise_stencil2d_backward_workspace(int64_t H, int64_t W, int32_t kh, int32_t kw) {
+  if (!dim_ok(H) || !dim_ok(W) || kh <= 0 || kw <= 0 || kh > 15 || kw > 15) return 0;
+  return stencil_backward_workspace((int)H, (int)W, kh, kw);
+}
+
+rise_status rise_stencil2d_backward(float* dIn, int64_t ld_din, float* dW, const float* dOut,
+                                    int64_t ld_dout, const float* in, int64_t ld_in, int64_t H,
+                                    int64_t W, const float* w, int32_t kh, int32_t kw,
+                                    rise_pad pad, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!dim_ok(H) || !dim_ok(W))
+    return fail(RISE_ERR_SHAPE, "rise_stencil2d_backward: sizes must be in [0, 2^31)");
+  if (kh <= 0 || kw <= 0 || kh % 2 == 0 || kw % 2 == 0 || kh > 15 || kw > 15)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d_backward: window sides must be odd, <= 15");
+  if (pad != RISE_PAD_CLAMP && pad != RISE_PAD_ZERO)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d_backward: unknown pad mode");
+  if (!dIn && !dW) return RISE_OK;
+  if (H == 0 || W == 0) {
+    if (dW) return fail(RISE_ERR_SHAPE, "rise_stencil2d_backward: dW of an empty image");
+    return RISE_OK;
+  }
+  if (!dOut) return fail(RISE_ERR_NULL, "rise_stencil2d_backward: dOut is NULL");
+  if (dIn && !w) return fail(RISE_ERR_NULL, "rise_stencil2d_backward: w is NULL");
+  if (dW && !in) return fail(RISE_ERR_NULL, "rise_stencil2d_backward: in is NULL");
+  if (ld_dout < W || (dIn && ld_din < W) || (dW && ld_in < W))
+    return fail(RISE_ERR_SHAPE, "rise_stencil2d_backward: ld below W");
+  size_t need = stencil_backward_workspace((int)H, (int)W, kh, kw);
+  if (!ws || ws_bytes < need)
+    return fail(RISE_ERR_WORKSPACE, "rise_stencil2d_backward: workspace too small");
+  if ((uintptr_t)ws & 255)
+    return fail(RISE_ERR_WORKSPACE, "rise_stencil2d_backward: workspace must be 256-byte aligned");
+  Range rws{(uintptr_t)ws, (uintptr_t)ws + need};
+  Range rg = span(dOut, H, W, ld_dout, 4);
+  Range rin = dW ? span(in, H, W, ld_in, 4) : Range{0, 0};
+  Range rwt = dIn ? span(w, kh, kw, kw, 4) : Range{0, 0};
+  Range rdi = dIn ? span(dIn, H, W, ld_din, 4) : Range{0, 0};
+  Range rdw = dW ? span(dW, kh, kw, kw, 4) : Range{0, 0};
+  for (Range o : {rdi, rdw, rws})
+    for (Range i : {rg, rin, rwt})
+      if (overlaps(o, i)) return fail(RISE_ERR_ALIAS, "rise_stencil2d_backward: output overlaps input");
+  if (overlaps(rdi, rdw) || overlaps(rdi, rws) || overlaps(rdw, rws))
+    return fail(RISE_ERR_ALIAS, "rise_stencil2d_backward: outputs overlap");
+  StencilBwdArgs a{dIn, ld_din, dW, dOut, ld_dout, in, ld_in, (int)H, (int)W, w, kh, kw, (int)pad};
+  return launch_stencil2d_backward(a, ws, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -83,4 +83,20 @@ bool stencil_schedule_supported(const rise_stencil_schedule& sc);
 rise_stencil_schedule stencil_default_schedule(int H, int W, int kh, int kw);
 rise_status launch_stencil2d(const StencilArgs& a, const rise_stencil_schedule& sc, hipStream_t s);
 
+struct StencilBwdArgs {
+  float* din;  // may be null
+  int64_t ld_din;
+  float* dw;   // may be null
+  const float* dout;
+  int64_t ld_dout;
+  const float* in;
+  int64_t ld_in;
+  int H, W;
+  const float* w;
+  int kh, kw;
+  int pad;
+};
+size_t stencil_backward_workspace(int H, int W, int kh, int kw);
+rise_status launch_stencil2d_backward(const StencilBwdArgs& a, void* ws, hipStream_t s);
+
 }  // namespace rise

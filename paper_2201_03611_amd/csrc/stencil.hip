@@ -372,4 +372,298 @@ rise_status launch_stencil2d(const StencilArgs& a, const rise_stencil_schedule& 
   return check_launch("stencil2d_direct");
 }
 
+
+// ===========================================================================
+// Adjoint of the stencil (backward).
+//
+// dIn: the stencil is linear in its input, out = S in, and dIn = S^T dOut.
+//   zero pad:  S^T is the stencil with the window rotated by 180 degrees applied
+//              to dOut with zero padding (a window element at offset (dy, dx)
+//              becomes the element at (-dy, -dx));
+//   clamp pad: the same everywhere except the first/last row and column, which
+//              also collect the contributions clamped onto them:
+//              dIn[p] = sum_d w[d] sum { dOut[o] : clamp(o + d - r) = p },
+//              evaluated separately per dimension.
+// dW:  dW[dy][dx] = sum over outputs (y, x) of dOut[y][x] * window(y, x)[dy][dx],
+//      a reduction over all pixels: per-wave partial sums (streaming the input
+//      like the forward kernel) then one deterministic reduction.
+// ===========================================================================
+namespace {
+
+__global__ void rotate180_kernel(float* __restrict__ dst, const float* __restrict__ w, int n) {
+  int t = threadIdx.x + blockIdx.x * blockDim.x;
+  if (t < n) dst[t] = w[n - 1 - t];
+}
+
+// o range of {o in [0, N) : clamp(o + d - r, 0, N - 1) == p}
+__device__ __forceinline__ void clamp_preimage(int p, int d, int r, int N, int& lo, int& hi) {
+  const int exact = p - d + r;
+  lo = (p == 0) ? 0 : exact;
+  hi = (p == N - 1) ? N - 1 : exact;
+  if (lo < 0) lo = 0;
+  if (hi > N - 1) hi = N - 1;
+}
+
+__global__ __launch_bounds__(kThreads) void adjoint_clamp_border(
+    float* __restrict__ din, int64_t ld_din, const float* __restrict__ dout, int64_t ld_dout,
+    int H, int W, const float* __restrict__ w, int kh, int kw) {
+  // border pixels: row 0, row H-1, then column 0 and column W-1 of rows 1..H-2
+  const int n_top = W, n_bot = H > 1 ? W : 0, n_mid = H > 2 ? H - 2 : 0;
+  const int n_side = W > 1 ? 2 * n_mid : n_mid;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int py, px;
+  if (i < n_top) {
+    py = 0; px = i;
+  } else if ((i -= n_top) < n_bot) {
+    py = H - 1; px = i;
+  } else if ((i -= n_bot) < n_side) {
+    py = 1 + (i % n_mid);
+    px = (i < n_mid) ? 0 : W - 1;
+  } else {
+    return;
+  }
+  const int rh = (kh - 1) / 2, rw = (kw - 1) / 2;
+  float acc = 0.f;
+  for (int dy = 0; dy < kh; dy++) {
+    int ylo, yhi;
+    clamp_preimage(py, dy, rh, H, ylo, yhi);
+    for (int dx = 0; dx < kw; dx++) {
+      int xlo, xhi;
+      clamp_preimage(px, dx, rw, W, xlo, xhi);
+      float s = 0.f;
+      for (int oy = ylo; oy <= yhi; oy++)
+        for (int ox = xlo; ox <= xhi; ox++) s += dout[(int64_t)oy * ld_dout + ox];
+      acc = fmaf(w[dy * kw + dx], s, acc);
+    }
+  }
+  din[(int64_t)py * ld_din + px] = acc;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Per-wave partial sums of dW over one 256-column strip segment of L output rows.
+template <int K, bool VEC, int L>
+__global__ __launch_bounds__(kThreads) void stencil_dw_stream(
+    float* __restrict__ partial, const float* __restrict__ dout, int64_t ld_dout,
+    const float* __restrict__ in, int64_t ld_in, int H, int W, int zero_pad, int segs,
+    int tasks) {
+  constexpr int R = (K - 1) / 2;
+  constexpr int P = K >= 4 ? K : K * ((4 + K - 1) / K);
+  constexpr int NIN = L + 2 * R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int task = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wave;
+  if (task >= tasks) return;
+  const int strip = task / segs, seg = task - strip * segs;
+  const int x0 = strip * TX, x = x0 + 4 * lane;
+  const int ys = seg * L;
+  const int edge_x = lane == 0 ? x0 - 4 : x0 + TX;
+  const bool edge_lane = lane == 0 || lane == 63;
+
+  f32x4 raw[P], edge[P], grad[P];
+  float win[K][12];
+  float acc[K][K];
+#pragma unroll
+  for (int p = 0; p < P; p++) edge[p] = grad[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int dy = 0; dy < K; dy++)
+#pragma unroll
+    for (int dx = 0; dx < K; dx++) acc[dy][dx] = 0.f;
+
+  // dOut chunk of output row o (zero outside the image: those outputs do not exist)
+  auto fetch_grad = [&](int o) -> f32x4 {
+    const int y = ys + o;
+    if (o < 0 || o >= L || y >= H) return f32x4{0.f, 0.f, 0.f, 0.f};
+    const float* rp = dout + (int64_t)y * ld_dout;
+    if (VEC && x + 3 < W) return *reinterpret_cast<const f32x4*>(rp + x);
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (x + 0 < W) v.x = rp[x + 0];
+    if (x + 1 < W) v.y = rp[x + 1];
+    if (x + 2 < W) v.z = rp[x + 2];
+    if (x + 3 < W) v.w = rp[x + 3];
+    return v;
+  };
+  auto fetch = [&](int t, int slot) {
+    const int gy = ys - R + t;
+    raw[slot] = load_chunk4<VEC>(in, ld_in, H, W, gy, x, zero_pad);
+    if (edge_lane) edge[slot] = load_chunk4<VEC>(in, ld_in, H, W, gy, edge_x, zero_pad);
+    grad[slot] = fetch_grad(t - 2 * R);  // the output row this input row completes
+  };
+
+#pragma unroll
+  for (int p = 0; p < P; p++)
+    if (p < NIN) fetch(p, p);
+
+  for (int t0 = 0; t0 < NIN; t0 += P) {
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      const int t = t0 + p;
+      if (t >= NIN) break;
+      float* row = win[p % K];
+      const f32x4 c = raw[p];
+      const f32x4 e = edge[p];
+      const f32x4 g = grad[p];
+      row[4] = c.x; row[5] = c.y; row[6] = c.z; row[7] = c.w;
+      if (R > 0) {
+        float l0 = wave_from_left(c.x), l1 = wave_from_left(c.y);
+        float l2 = wave_from_left(c.z), l3 = wave_from_left(c.w);
+        float r0 = wave_from_right(c.x), r1 = wave_from_right(c.y);
+        float r2 = wave_from_right(c.z), r3 = wave_from_right(c.w);
+        if (lane == 0) { l0 = e.x; l1 = e.y; l2 = e.z; l3 = e.w; }
+        if (lane == 63) { r0 = e.x; r1 = e.y; r2 = e.z; r3 = e.w; }
+        row[0] = l0; row[1] = l1; row[2] = l2; row[3] = l3;
+        row[8] = r0; row[9] = r1; row[10] = r2; row[11] = r3;
+      }
+      if (t + P < NIN) fetch(t + P, p);
+      if (t >= 2 * R) {
+        const float gq[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+        for (int dy = 0; dy < K; dy++)
+#pragma unroll
+          for (int dx = 0; dx < K; dx++) {
+            float a = acc[dy][dx];
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+              a = fmaf(gq[q], win[(p + K - 2 * R + dy) % K][4 + q + dx - R], a);
+            acc[dy][dx] = a;
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int dy = 0; dy < K; dy++)
+#pragma unroll
+    for (int dx = 0; dx < K; dx++) {
+      float v = wave_sum(acc[dy][dx]);
+      if (lane == 0) partial[(int64_t)task * K * K + dy * K + dx] = v;
+    }
+}
+
+// Any odd kh x kw: block (chunk, tap) sums dOut * window over a chunk of pixels.
+__global__ __launch_bounds__(kThreads) void stencil_dw_direct(
+    float* __restrict__ partial, const float* __restrict__ dout, int64_t ld_dout,
+    const float* __restrict__ in, int64_t ld_in, int H, int W, int kh, int kw, int zero_pad,
+    int chunk) {
+  const int tap = blockIdx.y, dy = tap / kw, dx = tap - dy * kw;
+  const int rh = (kh - 1) / 2, rw = (kw - 1) / 2;
+  const int64_t n = (int64_t)H * W;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk;
+  float acc = 0.f;
+  for (int64_t i = p0 + threadIdx.x; i < p0 + chunk && i < n; i += kThreads) {
+    const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
+    int yy = y + dy - rh, xx = x + dx - rw;
+    const bool inside = yy >= 0 && yy < H && xx >= 0 && xx < W;
+    if (!inside && zero_pad) continue;
+    yy = clampi(yy, 0, H - 1);
+    xx = clampi(xx, 0, W - 1);
+    acc = fmaf(dout[(int64_t)y * ld_dout + x], in[(int64_t)yy * ld_in + xx], acc);
+  }
+  __shared__ float red[kThreads / 64];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int q = 0; q < kThreads / 64; q++) s += red[q];
+    partial[(int64_t)blockIdx.x * gridDim.y + tap] = s;
+  }
+}
+
+// dW[t] = sum over parts of partial[part][t] (one block per tap, fixed order).
+__global__ __launch_bounds__(kThreads) void reduce_partials(float* __restrict__ dW,
+                                                            const float* __restrict__ partial,
+                                                            int parts, int taps) {
+  const int t = blockIdx.x;
+  float acc = 0.f;
+  for (int p = threadIdx.x; p < parts; p += kThreads) acc += partial[(int64_t)p * taps + t];
+  __shared__ float red[kThreads / 64];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int q = 0; q < kThreads / 64; q++) s += red[q];
+    dW[t] = s;
+  }
+}
+
+constexpr int kDwRows = 32;       // output rows per wave in the streaming dW kernel
+constexpr int kDwChunk = 65536;   // pixels per block in the direct dW kernel
+
+bool dw_streaming(int kh, int kw) { return kh == kw && (kh == 1 || kh == 3 || kh == 5 || kh == 7); }
+
+int64_t dw_parts(int H, int W, int kh, int kw) {
+  if (dw_streaming(kh, kw)) {
+    int64_t strips = (W + TX - 1) / TX, segs = (H + kDwRows - 1) / kDwRows;
+    return strips * segs;
+  }
+  return ((int64_t)H * W + kDwChunk - 1) / kDwChunk;
+}
+
+template <int K, bool VEC>
+rise_status launch_dw_stream(float* partial, const StencilBwdArgs& a, hipStream_t s) {
+  int strips = (a.W + TX - 1) / TX, segs = (a.H + kDwRows - 1) / kDwRows;
+  int tasks = strips * segs;
+  hipLaunchKernelGGL((stencil_dw_stream<K, VEC, kDwRows>), dim3((tasks + 3) / 4), dim3(kThreads),
+                     0, s, partial, a.dout, a.ld_dout, a.in, a.ld_in, a.H, a.W,
+                     (int)(a.pad == RISE_PAD_ZERO), segs, tasks);
+  return check_launch("stencil_dw_stream");
+}
+
+}  // namespace
+
+size_t stencil_backward_workspace(int H, int W, int kh, int kw) {
+  size_t rot = 256;  // rotated weights (kh * kw <= 225 floats = 900 bytes, rounded below)
+  rot = ((size_t)kh * kw * 4 + 255) / 256 * 256;
+  size_t part = (size_t)dw_parts(H, W, kh, kw) * kh * kw * 4;
+  return rot + part;
+}
+
+rise_status launch_stencil2d_backward(const StencilBwdArgs& a, void* ws, hipStream_t s) {
+  const int taps = a.kh * a.kw;
+  float* rot = (float*)ws;
+  float* partial = (float*)((char*)ws + ((size_t)taps * 4 + 255) / 256 * 256);
+  rise_status st = RISE_OK;
+  if (a.din) {
+    hipLaunchKernelGGL(rotate180_kernel, dim3(1), dim3(256), 0, s, rot, a.w, taps);
+    if ((st = check_launch("rotate180_kernel")) != RISE_OK) return st;
+    StencilArgs f{a.din, a.ld_din, a.dout, a.ld_dout, a.H, a.W, rot, a.kh, a.kw, RISE_PAD_ZERO};
+    st = launch_stencil2d(f, stencil_default_schedule(a.H, a.W, a.kh, a.kw), s);
+    if (st != RISE_OK) return st;
+    if (a.pad == RISE_PAD_CLAMP) {
+      int n = a.W + (a.H > 1 ? a.W : 0) + (a.H > 2 ? (a.W > 1 ? 2 : 1) * (a.H - 2) : 0);
+      hipLaunchKernelGGL(adjoint_clamp_border, dim3((n + kThreads - 1) / kThreads),
+                         dim3(kThreads), 0, s, a.din, a.ld_din, a.dout, a.ld_dout, a.H, a.W,
+                         a.w, a.kh, a.kw);
+      if ((st = check_launch("adjoint_clamp_border")) != RISE_OK) return st;
+    }
+  }
+  if (a.dw) {
+    const int64_t parts = dw_parts(a.H, a.W, a.kh, a.kw);
+    auto aligned = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    bool vec = aligned(a.in) && aligned(a.dout) && a.ld_in % 4 == 0 && a.ld_dout % 4 == 0;
+    if (dw_streaming(a.kh, a.kw)) {
+      switch (a.kh) {
+        case 1: st = vec ? launch_dw_stream<1, true>(partial, a, s) : launch_dw_stream<1, false>(partial, a, s); break;
+        case 3: st = vec ? launch_dw_stream<3, true>(partial, a, s) : launch_dw_stream<3, false>(partial, a, s); break;
+        case 5: st = vec ? launch_dw_stream<5, true>(partial, a, s) : launch_dw_stream<5, false>(partial, a, s); break;
+        default: st = vec ? launch_dw_stream<7, true>(partial, a, s) : launch_dw_stream<7, false>(partial, a, s); break;
+      }
+    } else {
+      hipLaunchKernelGGL(stencil_dw_direct, dim3((unsigned)parts, (unsigned)taps), dim3(kThreads),
+                         0, s, partial, a.dout, a.ld_dout, a.in, a.ld_in, a.H, a.W, a.kh, a.kw,
+                         (int)(a.pad == RISE_PAD_ZERO), kDwChunk);
+      st = check_launch("stencil_dw_direct");
+    }
+    if (st != RISE_OK) return st;
+    hipLaunchKernelGGL(reduce_partials, dim3(taps), dim3(kThreads), 0, s, a.dw, partial,
+                       (int)parts, taps);
+    if ((st = check_launch("reduce_partials")) != RISE_OK) return st;
+  }
+  return RISE_OK;
+}
+
 }  // namespace rise

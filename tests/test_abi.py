@@ -135,3 +135,33 @@ def test_prep_rejections(lib):
 def test_status_strings(lib):
     for s in range(8):
         assert lib.rise_status_string(s)
+
+
+def test_backward_rejections(lib):
+    GB = lib.rise_gemm_backward
+    # dA overlapping dC
+    assert GB(FAKE_C, 64, None, 0, FAKE_C + 64, 64, FAKE_A, 64, FAKE_B, 64, 64, 64, 64, 0, None, 0,
+              None) == 3
+    assert GB(None, 0, None, 0, FAKE_C, 64, FAKE_A, 64, FAKE_B, 64, -1, 64, 64, 0, None, 0,
+              None) == 2
+    assert GB(None, 0, None, 0, FAKE_C, 64, FAKE_A, 64, FAKE_B, 64, 64, 64, 64, 0, None, 0,
+              None) == 0  # nothing requested
+    SB = lib.rise_stencil2d_backward
+    need = lib.rise_stencil2d_backward_workspace(64, 64, 5, 5)
+    assert need > 0
+    args = dict(dIn=FAKE_C, ld_din=64, dW=0x60000000, dOut=FAKE_A, ld_dout=64, inp=FAKE_B,
+                ld_in=64, H=64, W=64, w=FAKE_W, kh=5, kw=5, pad=0, ws=0x70000000, wsb=need)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return SB(a["dIn"], a["ld_din"], a["dW"], a["dOut"], a["ld_dout"], a["inp"], a["ld_in"],
+                  a["H"], a["W"], a["w"], a["kh"], a["kw"], a["pad"], a["ws"], a["wsb"], None)
+
+    assert call(kh=4) == 5
+    assert call(dOut=None) == 1
+    assert call(wsb=need - 1) == 6
+    assert call(ws=0x70000001) == 6
+    assert call(dIn=FAKE_A) == 3
+    assert call(dW=FAKE_C + 8) == 3
+    assert call(ld_din=10) == 2
+    assert call(dIn=None, dW=None) == 0
