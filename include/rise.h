@@ -200,6 +200,40 @@ rise_status rise_stencil2d_backward(float* dIn, int64_t ld_din, float* dW, const
                                     int64_t W, const float* w, int32_t kh, int32_t kw,
                                     rise_pad pad, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Multi-channel stencil layer (convolution layer), NHWC bfloat16           */
+/* ------------------------------------------------------------------------ */
+
+/* out[b][y][x][co] = reduce(+, 0) over ci of
+ *     stencil(pad2D(in[b][.][.][ci]), w[co][ci])
+ * i.e. the 2D stencil above (cross-correlation order) summed over input
+ * channels (the multi-channel reading of the stencil pattern; the paper defines
+ * no convolution layer).  in: B x H x W x Cin and out: B x H x W x Cout are
+ * bfloat16 bit patterns (NHWC, 16-byte aligned); w: Cout x Cin x kh x kw FP32,
+ * rounded to bfloat16 (nearest even) for the matrix cores; FP32 accumulation,
+ * output rounded to bfloat16.  Supported: kh = kw = 3, Cin in {16, 32, 64},
+ * Cout in {32, 64}; other shapes return RISE_ERR_UNSUPPORTED.  Workspace:
+ * rise_conv2d_workspace(Cin, Cout) bytes (the prepared weights). */
+size_t rise_conv2d_workspace(int32_t Cin, int32_t Cout);
+rise_status rise_conv2d(uint16_t* out, const uint16_t* in, const float* w, int32_t B, int32_t Cin,
+                        int32_t Cout, int32_t H, int32_t W, int32_t kh, int32_t kw, rise_pad pad,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Gradients of L(out), out = rise_conv2d(in, w), given dOut (B x H x W x Cout,
+ * bfloat16 NHWC):
+ *   dIn (B x H x W x Cin, bfloat16) = the layer applied to dOut with the channel
+ *       roles swapped and the window rotated by 180 degrees (the adjoint of zero
+ *       padding; clamp padding is rejected when dIn is requested);
+ *   dW  (Cout x Cin x 3 x 3, FP32) = sum over (b, y, x) of
+ *       dOut[b][y][x][co] * window_ci(b, y, x)[dy][dx], reduced in a fixed order.
+ * Either output may be NULL.  Supported: Cin and Cout in {32, 64}, kh = kw = 3.
+ * Workspace: rise_conv2d_backward_workspace(B, Cin, Cout, H, W) bytes. */
+size_t rise_conv2d_backward_workspace(int32_t B, int32_t Cin, int32_t Cout, int32_t H, int32_t W);
+rise_status rise_conv2d_backward(uint16_t* dIn, float* dW, const uint16_t* dOut,
+                                 const uint16_t* in, const float* w, int32_t B, int32_t Cin,
+                                 int32_t Cout, int32_t H, int32_t W, int32_t kh, int32_t kw,
+                                 rise_pad pad, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

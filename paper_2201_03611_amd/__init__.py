@@ -162,6 +162,34 @@ def rise_stencil2d_backward(dIn, dW, dOut, inp, w, H, W, *, ld_din, ld_dout, ld_
     _check(st, "rise_stencil2d_backward")
 
 
+def rise_conv2d_workspace(Cin, Cout):
+    return int(lib.rise_conv2d_workspace(Cin, Cout))
+
+
+def rise_conv2d(out, inp, w, B, Cin, Cout, H, W, *, kh=3, kw=3, pad="zero", ws=None, stream=None):
+    """out, inp: bfloat16 NHWC device tensors; w: Cout x Cin x kh x kw float32."""
+    _require_cuda(out, inp, w, ws)
+    p = PADS[pad] if isinstance(pad, str) else int(pad)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    st = lib.rise_conv2d(_ptr(out), _ptr(inp), _ptr(w), B, Cin, Cout, H, W, kh, kw, p, _ptr(ws),
+                         ws_bytes, _stream(stream))
+    _check(st, "rise_conv2d")
+
+
+def rise_conv2d_backward_workspace(B, Cin, Cout, H, W):
+    return int(lib.rise_conv2d_backward_workspace(B, Cin, Cout, H, W))
+
+
+def rise_conv2d_backward(dIn, dW, dOut, inp, w, B, Cin, Cout, H, W, *, kh=3, kw=3, pad="zero",
+                         ws=None, stream=None):
+    _require_cuda(dIn, dW, dOut, inp, w, ws)
+    p = PADS[pad] if isinstance(pad, str) else int(pad)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    st = lib.rise_conv2d_backward(_ptr(dIn), _ptr(dW), _ptr(dOut), _ptr(inp), _ptr(w), B, Cin,
+                                  Cout, H, W, kh, kw, p, _ptr(ws), ws_bytes, _stream(stream))
+    _check(st, "rise_conv2d_backward")
+
+
 # ---------------------------------------------------------------------------
 # convenience wrappers
 # ---------------------------------------------------------------------------
@@ -234,4 +262,31 @@ def stencil2d_backward(dOut, img, w, pad="clamp", *, need_din=True, need_dw=True
     return dIn, dW
 
 
-from .autograd import RiseGemmFn, RiseStencil2dFn  # noqa: E402,F401
+def conv2d(x, w, pad="zero", stream=None):
+    """x: B x H x W x Cin bfloat16 (NHWC), w: Cout x Cin x 3 x 3 float32 -> bfloat16 NHWC."""
+    x = x.contiguous()
+    w = w.contiguous().to(device=x.device, dtype=torch.float32)
+    B, H, W, Cin = x.shape
+    Cout = w.shape[0]
+    out = torch.empty((B, H, W, Cout), device=x.device, dtype=torch.bfloat16)
+    ws = torch.empty(rise_conv2d_workspace(Cin, Cout), device=x.device, dtype=torch.uint8)
+    rise_conv2d(out, x, w, B, Cin, Cout, H, W, kh=w.shape[2], kw=w.shape[3], pad=pad, ws=ws,
+                stream=stream)
+    return out
+
+
+def conv2d_backward(dOut, x, w, pad="zero", *, need_din=True, need_dw=True, stream=None):
+    dOut, x = dOut.contiguous(), x.contiguous()
+    w = w.contiguous().to(device=x.device, dtype=torch.float32)
+    B, H, W, Cin = x.shape
+    Cout = w.shape[0]
+    dIn = torch.empty_like(x) if need_din else None
+    dW = torch.empty_like(w) if need_dw else None
+    ws = torch.empty(rise_conv2d_backward_workspace(B, Cin, Cout, H, W), device=x.device,
+                     dtype=torch.uint8)
+    rise_conv2d_backward(dIn, dW, dOut, x, w, B, Cin, Cout, H, W, kh=w.shape[2], kw=w.shape[3],
+                         pad=pad, ws=ws, stream=stream)
+    return dIn, dW
+
+
+from .autograd import RiseConv2dFn, RiseGemmFn, RiseStencil2dFn  # noqa: E402,F401

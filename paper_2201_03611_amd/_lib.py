@@ -53,6 +53,12 @@ SIGNATURES = {
     "rise_stencil_schedules": (_I32, [ctypes.POINTER(RiseStencilSchedule), _I32]),
     "rise_stencil2d": (_INT, [_P, _I64, _P, _I64, _I64, _I64, _P, _I32, _I32, _INT,
                               ctypes.POINTER(RiseStencilSchedule), _P]),
+    "rise_conv2d_workspace": (_SZ, [_I32, _I32]),
+    "rise_conv2d": (_INT, [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _INT, _P, _SZ,
+                           _P]),
+    "rise_conv2d_backward_workspace": (_SZ, [_I32, _I32, _I32, _I32, _I32]),
+    "rise_conv2d_backward": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32,
+                                    _INT, _P, _SZ, _P]),
     "rise_stencil2d_backward_workspace": (_SZ, [_I64, _I64, _I32, _I32]),
     "rise_stencil2d_backward": (_INT, [_P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64, _P, _I32,
                                        _I32, _INT, _P, _SZ, _P]),

@@ -45,3 +45,24 @@ class RiseStencil2dFn(torch.autograd.Function):
                                      need_din=ctx.needs_input_grad[0],
                                      need_dw=ctx.needs_input_grad[1])
         return dIn, dW, None
+
+
+class RiseConv2dFn(torch.autograd.Function):
+    """Stencil layer: bfloat16 NHWC activations, FP32 weights, 3 x 3, zero padding."""
+
+    @staticmethod
+    def forward(ctx, x, w):
+        from . import conv2d
+
+        ctx.save_for_backward(x, w)
+        return conv2d(x, w, pad="zero")
+
+    @staticmethod
+    def backward(ctx, dOut):
+        from . import conv2d_backward
+
+        x, w = ctx.saved_tensors
+        dIn, dW = conv2d_backward(dOut.to(torch.bfloat16), x, w, pad="zero",
+                                  need_din=ctx.needs_input_grad[0],
+                                  need_dw=ctx.needs_input_grad[1])
+        return dIn, dW

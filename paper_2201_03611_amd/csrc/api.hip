@@ -7,6 +7,7 @@
 #include <string>
 
 #include "common.h"
+#include "conv.h"
 #include "gemm_lowp.h"
 
 namespace rise {
@@ -284,6 +285,94 @@ rise_status rise_stencil2d_backward(float* dIn, int64_t ld_din, float* dW, const
     return fail(RISE_ERR_ALIAS, "rise_stencil2d_backward: outputs overlap");
   StencilBwdArgs a{dIn, ld_din, dW, dOut, ld_dout, in, ld_in, (int)H, (int)W, w, kh, kw, (int)pad};
   return launch_stencil2d_backward(a, ws, (hipStream_t)stream);
+}
+
+namespace {
+bool conv_dims_ok(int64_t B, int64_t Cin, int64_t Cout, int64_t H, int64_t W) {
+  return B >= 0 && H >= 0 && W >= 0 && dim_ok(B * H * W) && Cin > 0 && Cout > 0;
+}
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+}  // namespace
+
+size_t rise_conv2d_workspace(int32_t Cin, int32_t Cout) {
+  if (Cin <= 0 || Cout <= 0) return 0;
+  return conv_forward_workspace(Cin, Cout);
+}
+
+rise_status rise_conv2d(uint16_t* out, const uint16_t* in, const float* w, int32_t B, int32_t Cin,
+                        int32_t Cout, int32_t H, int32_t W, int32_t kh, int32_t kw, rise_pad pad,
+                        void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!conv_dims_ok(B, Cin, Cout, H, W)) return fail(RISE_ERR_SHAPE, "rise_conv2d: sizes");
+  if (pad != RISE_PAD_CLAMP && pad != RISE_PAD_ZERO)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_conv2d: unknown pad mode");
+  if (!conv_supported(Cin, Cout, kh, kw, false))
+    return fail(RISE_ERR_UNSUPPORTED, "rise_conv2d: needs a 3x3 window, Cin in {16,32,64}, "
+                                      "Cout in {32,64}");
+  if (B == 0 || H == 0 || W == 0) return RISE_OK;
+  if (!out || !in || !w) return fail(RISE_ERR_NULL, "rise_conv2d: NULL pointer");
+  if (!aligned16(out) || !aligned16(in))
+    return fail(RISE_ERR_SHAPE, "rise_conv2d: activations must be 16-byte aligned");
+  size_t need = conv_forward_workspace(Cin, Cout);
+  if (!ws || ws_bytes < need) return fail(RISE_ERR_WORKSPACE, "rise_conv2d: workspace too small");
+  if ((uintptr_t)ws & 255) return fail(RISE_ERR_WORKSPACE, "rise_conv2d: workspace alignment");
+  const int64_t px = (int64_t)B * H * W;
+  Range ro{(uintptr_t)out, (uintptr_t)out + (uintptr_t)(px * Cout * 2)};
+  Range ri{(uintptr_t)in, (uintptr_t)in + (uintptr_t)(px * Cin * 2)};
+  Range rw{(uintptr_t)w, (uintptr_t)w + (uintptr_t)Cout * Cin * 9 * 4};
+  Range rs{(uintptr_t)ws, (uintptr_t)ws + need};
+  if (overlaps(ro, ri) || overlaps(ro, rw) || overlaps(ro, rs) || overlaps(rs, ri) ||
+      overlaps(rs, rw))
+    return fail(RISE_ERR_ALIAS, "rise_conv2d: output or workspace overlaps an input");
+  ConvArgs a{out, in, w, B, Cin, Cout, H, W, pad == RISE_PAD_ZERO};
+  return launch_conv2d(a, ws, (hipStream_t)stream);
+}
+
+size_t rise_conv2d_backward_workspace(int32_t B, int32_t Cin, int32_t Cout, int32_t H, int32_t W) {
+  if (!conv_dims_ok(B, Cin, Cout, H, W)) return 0;
+  return conv_backward_workspace(B, Cin, Cout, H, W);
+}
+
+rise_status rise_conv2d_backward(uint16_t* dIn, float* dW, const uint16_t* dOut,
+                                 const uint16_t* in, const float* w, int32_t B, int32_t Cin,
+                                 int32_t Cout, int32_t H, int32_t W, int32_t kh, int32_t kw,
+                                 rise_pad pad, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!conv_dims_ok(B, Cin, Cout, H, W)) return fail(RISE_ERR_SHAPE, "rise_conv2d_backward: sizes");
+  if (pad != RISE_PAD_CLAMP && pad != RISE_PAD_ZERO)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_conv2d_backward: unknown pad mode");
+  if (!conv_supported(Cin, Cout, kh, kw, true))
+    return fail(RISE_ERR_UNSUPPORTED, "rise_conv2d_backward: needs a 3x3 window, Cin and Cout "
+                                      "in {32,64}");
+  if (dIn && pad != RISE_PAD_ZERO)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_conv2d_backward: dIn is implemented for zero padding");
+  if (!dIn && !dW) return RISE_OK;
+  if (B == 0 || H == 0 || W == 0) {
+    if (dW) return fail(RISE_ERR_SHAPE, "rise_conv2d_backward: dW of an empty batch");
+    return RISE_OK;
+  }
+  if (!dOut || (dIn && !w) || (dW && !in)) return fail(RISE_ERR_NULL, "rise_conv2d_backward: NULL");
+  if (!aligned16(dOut) || (dIn && !aligned16(dIn)) || (dW && !aligned16(in)))
+    return fail(RISE_ERR_SHAPE, "rise_conv2d_backward: activations must be 16-byte aligned");
+  size_t need = conv_backward_workspace(B, Cin, Cout, H, W);
+  if (!ws || ws_bytes < need)
+    return fail(RISE_ERR_WORKSPACE, "rise_conv2d_backward: workspace too small");
+  if ((uintptr_t)ws & 255)
+    return fail(RISE_ERR_WORKSPACE, "rise_conv2d_backward: workspace alignment");
+  const int64_t px = (int64_t)B * H * W;
+  Range rdi = dIn ? Range{(uintptr_t)dIn, (uintptr_t)dIn + (uintptr_t)(px * Cin * 2)} : Range{0, 0};
+  Range rdw = dW ? Range{(uintptr_t)dW, (uintptr_t)dW + (uintptr_t)Cout * Cin * 9 * 4} : Range{0, 0};
+  Range rs{(uintptr_t)ws, (uintptr_t)ws + need};
+  Range rg{(uintptr_t)dOut, (uintptr_t)dOut + (uintptr_t)(px * Cout * 2)};
+  Range rin = dW ? Range{(uintptr_t)in, (uintptr_t)in + (uintptr_t)(px * Cin * 2)} : Range{0, 0};
+  Range rwt = dIn ? Range{(uintptr_t)w, (uintptr_t)w + (uintptr_t)Cout * Cin * 9 * 4} : Range{0, 0};
+  for (Range o : {rdi, rdw, rs})
+    for (Range i : {rg, rin, rwt})
+      if (overlaps(o, i)) return fail(RISE_ERR_ALIAS, "rise_conv2d_backward: output overlaps input");
+  if (overlaps(rdi, rdw) || overlaps(rdi, rs) || overlaps(rdw, rs))
+    return fail(RISE_ERR_ALIAS, "rise_conv2d_backward: outputs overlap");
+  ConvBwdArgs a{dIn, dW, dOut, in, w, B, Cin, Cout, H, W, pad == RISE_PAD_ZERO};
+  return launch_conv2d_backward(a, ws, (hipStream_t)stream);
 }
 
 }  // extern "C"
