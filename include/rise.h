@@ -234,6 +234,69 @@ rise_status rise_conv2d_backward(uint16_t* dIn, float* dW, const uint16_t* dOut,
                                  int32_t Cout, int32_t H, int32_t W, int32_t kh, int32_t kw,
                                  rise_pad pad, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched form: many problems, one persistent launch                        */
+/* ------------------------------------------------------------------------ */
+
+/* One GEMM of a batch: C (M x N, FP32, ldc) = A (M x K, row-major, lda) . B,
+ * B stored K x N (opB = RISE_OP_N) or N x K (RISE_OP_T), ldb; A and B of type
+ * dtype (RISE_F32, or RISE_BF16 with FP32 accumulation).  Batched operands must
+ * be 16-byte aligned with lda, ldb multiples of 16 bytes; bf16 also needs K (and
+ * N when opB = RISE_OP_N) multiples of 8. */
+typedef struct {
+  float* C;
+  const void* A;
+  const void* B;
+  int64_t M, N, K, lda, ldb, ldc;
+  int32_t dtype; /* rise_dtype */
+  int32_t opB;   /* rise_op */
+} rise_gemm_problem;
+
+/* One stencil of a batch: as rise_stencil2d with a square window of side k in
+ * {1, 3, 5, 7}; images 16-byte aligned with ld_in, ld_out multiples of 4. */
+typedef struct {
+  float* out;
+  const float* in;
+  const float* w;
+  int64_t H, W, ld_in, ld_out;
+  int32_t k;
+  int32_t pad; /* rise_pad */
+} rise_stencil_problem;
+
+/* A plan owns the device copy of the problem descriptors, the work-item list
+ * (every output tile of every problem, largest estimated cost first) and a HIP
+ * graph of  [reset the work counter] -> [one persistent kernel]  whose
+ * workgroups take items until none are left.  The batch is the outer map of
+ * the patterns: its items write distinct outputs, so any order is correct
+ * (distinct output acceptors, paper Sec. V-C).  GEMM tile shapes come from a
+ * per-tile cost table (tune_table: a file written by rise_autotune_batched, or
+ * NULL for the built-in MI355X table).  plan_create allocates device memory and
+ * synchronises; it is not meant for the hot path.  The problems' buffers must
+ * stay valid for every launch of the plan. */
+typedef struct rise_plan rise_plan;
+rise_status rise_plan_create(rise_plan** plan, const rise_gemm_problem* gemms, int32_t n_gemm,
+                             const rise_stencil_problem* stencils, int32_t n_stencil,
+                             const char* tune_table, void* stream);
+/* One launch of the captured graph on `stream`. */
+rise_status rise_plan_launch(rise_plan* plan, void* stream);
+/* The same two kernels launched directly (no graph), for comparison. */
+rise_status rise_plan_launch_direct(rise_plan* plan, void* stream);
+rise_status rise_plan_destroy(rise_plan* plan);
+/* Number of work items; the tile (bm, bn, bk) chosen for GEMM `problem`. */
+int32_t rise_plan_items(const rise_plan* plan);
+rise_status rise_plan_tile(const rise_plan* plan, int32_t problem, rise_tile* tile);
+
+/* Create a plan, launch it once, wait for `stream`, destroy the plan. */
+rise_status rise_gemm_batched(const rise_gemm_problem* gemms, int32_t n, void* stream);
+rise_status rise_stencil2d_batched(const rise_stencil_problem* stencils, int32_t n,
+                                   void* stream);
+
+/* Measure the per-tile cost of every tile kind of the persistent kernel on the
+ * current device (a + b * K microseconds per GEMM tile, a per stencil tile) and
+ * write the table to `table_path` (text, one "name a b" line per kind).  Uses
+ * about 400 MB of temporary device memory; synchronises. */
+rise_status rise_autotune_batched(const char* table_path, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,8 +14,8 @@ import torch
 from . import _lib
 from ._lib import (RISE_BF16, RISE_F32, RISE_MODE_BF16, RISE_MODE_BF16X3, RISE_MODE_BF16X6,
                    RISE_MODE_F32, RISE_MODE_FP8, RISE_OP_N, RISE_OP_T, RISE_PAD_CLAMP,
-                   RISE_PAD_ZERO, RISE_STENCIL_LDS_TILE, RISE_STENCIL_STREAM, RiseStencilSchedule,
-                   RiseTile)
+                   RISE_PAD_ZERO, RISE_STENCIL_LDS_TILE, RISE_STENCIL_STREAM, RiseGemmProblem,
+                   RiseStencilProblem, RiseStencilSchedule, RiseTile)
 
 lib = _lib.load()
 
@@ -188,6 +188,76 @@ def rise_conv2d_backward(dIn, dW, dOut, inp, w, B, Cin, Cout, H, W, *, kh=3, kw=
     st = lib.rise_conv2d_backward(_ptr(dIn), _ptr(dW), _ptr(dOut), _ptr(inp), _ptr(w), B, Cin,
                                   Cout, H, W, kh, kw, p, _ptr(ws), ws_bytes, _stream(stream))
     _check(st, "rise_conv2d_backward")
+
+
+def rise_plan_create(gemms, n_gemm, stencils, n_stencil, tune_table=None, stream=None):
+    """gemms / stencils: ctypes arrays of RiseGemmProblem / RiseStencilProblem."""
+    plan = ctypes.c_void_p()
+    tt = tune_table.encode() if tune_table else None
+    st = lib.rise_plan_create(ctypes.byref(plan), gemms if n_gemm else None, n_gemm,
+                              stencils if n_stencil else None, n_stencil, tt, _stream(stream))
+    _check(st, "rise_plan_create")
+    return plan
+
+
+def rise_plan_launch(plan, stream=None):
+    _check(lib.rise_plan_launch(plan, _stream(stream)), "rise_plan_launch")
+
+
+def rise_plan_launch_direct(plan, stream=None):
+    _check(lib.rise_plan_launch_direct(plan, _stream(stream)), "rise_plan_launch_direct")
+
+
+def rise_plan_destroy(plan):
+    _check(lib.rise_plan_destroy(plan), "rise_plan_destroy")
+
+
+def rise_plan_items(plan):
+    return int(lib.rise_plan_items(plan))
+
+
+def rise_plan_tile(plan, problem):
+    t = RiseTile()
+    _check(lib.rise_plan_tile(plan, problem, ctypes.byref(t)), "rise_plan_tile")
+    return (t.bm, t.bn, t.bk)
+
+
+def rise_gemm_batched(gemms, n, stream=None):
+    _check(lib.rise_gemm_batched(gemms, n, _stream(stream)), "rise_gemm_batched")
+
+
+def rise_stencil2d_batched(stencils, n, stream=None):
+    _check(lib.rise_stencil2d_batched(stencils, n, _stream(stream)), "rise_stencil2d_batched")
+
+
+def rise_autotune_batched(table_path, stream=None):
+    _check(lib.rise_autotune_batched(table_path.encode(), _stream(stream)),
+           "rise_autotune_batched")
+
+
+class Plan:
+    """Owning wrapper of a rise_plan (problem arrays are kept alive with it)."""
+
+    def __init__(self, gemms, n_gemm, stencils, n_stencil, tune_table=None, stream=None):
+        self._keep = (gemms, stencils)
+        self.handle = rise_plan_create(gemms, n_gemm, stencils, n_stencil, tune_table, stream)
+
+    def launch(self, stream=None):
+        rise_plan_launch(self.handle, stream)
+
+    def launch_direct(self, stream=None):
+        rise_plan_launch_direct(self.handle, stream)
+
+    def items(self):
+        return rise_plan_items(self.handle)
+
+    def tile(self, problem):
+        return rise_plan_tile(self.handle, problem)
+
+    def destroy(self):
+        if self.handle is not None:
+            rise_plan_destroy(self.handle)
+            self.handle = None
 
 
 # ---------------------------------------------------------------------------

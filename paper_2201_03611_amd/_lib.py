@@ -31,6 +31,19 @@ class RiseStencilSchedule(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
 
+class RiseGemmProblem(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_void_p), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldc", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("opB", ctypes.c_int32)]
+
+
+class RiseStencilProblem(ctypes.Structure):
+    _fields_ = [("out", ctypes.c_void_p), ("inp", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("H", ctypes.c_int64), ("W", ctypes.c_int64), ("ld_in", ctypes.c_int64),
+                ("ld_out", ctypes.c_int64), ("k", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
@@ -59,6 +72,16 @@ SIGNATURES = {
     "rise_conv2d_backward_workspace": (_SZ, [_I32, _I32, _I32, _I32, _I32]),
     "rise_conv2d_backward": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32,
                                     _INT, _P, _SZ, _P]),
+    "rise_plan_create": (_INT, [ctypes.POINTER(_P), ctypes.POINTER(RiseGemmProblem), _I32,
+                                ctypes.POINTER(RiseStencilProblem), _I32, ctypes.c_char_p, _P]),
+    "rise_plan_launch": (_INT, [_P, _P]),
+    "rise_plan_launch_direct": (_INT, [_P, _P]),
+    "rise_plan_destroy": (_INT, [_P]),
+    "rise_plan_items": (_I32, [_P]),
+    "rise_plan_tile": (_INT, [_P, _I32, ctypes.POINTER(RiseTile)]),
+    "rise_gemm_batched": (_INT, [ctypes.POINTER(RiseGemmProblem), _I32, _P]),
+    "rise_stencil2d_batched": (_INT, [ctypes.POINTER(RiseStencilProblem), _I32, _P]),
+    "rise_autotune_batched": (_INT, [ctypes.c_char_p, _P]),
     "rise_stencil2d_backward_workspace": (_SZ, [_I64, _I64, _I32, _I32]),
     "rise_stencil2d_backward": (_INT, [_P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64, _P, _I32,
                                        _I32, _INT, _P, _SZ, _P]),

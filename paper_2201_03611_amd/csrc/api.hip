@@ -2,11 +2,13 @@
 // dispatch to the kernels.  Every rejected call names its reason through
 // rise_last_error(); nothing is chosen silently.
 #include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
 #include <string>
 
 #include "common.h"
+#include "batched.h"
 #include "conv.h"
 #include "gemm_lowp.h"
 
@@ -373,6 +375,154 @@ rise_status rise_conv2d_backward(uint16_t* dIn, float* dW, const uint16_t* dOut,
     return fail(RISE_ERR_ALIAS, "rise_conv2d_backward: outputs overlap");
   ConvBwdArgs a{dIn, dW, dOut, in, w, B, Cin, Cout, H, W, pad == RISE_PAD_ZERO};
   return launch_conv2d_backward(a, ws, (hipStream_t)stream);
+}
+
+struct rise_plan {
+  rise::PlanImpl* impl;
+};
+
+rise_status rise_plan_create(rise_plan** plan, const rise_gemm_problem* gemms, int32_t n_gemm,
+                             const rise_stencil_problem* stencils, int32_t n_stencil,
+                             const char* tune_table, void* stream) {
+  clear_error();
+  if (!plan) return fail(RISE_ERR_NULL, "rise_plan_create: plan is NULL");
+  *plan = nullptr;
+  PlanImpl* impl = nullptr;
+  rise_status st = plan_build(&impl, gemms, n_gemm, stencils, n_stencil, tune_table, -1,
+                              (hipStream_t)stream);
+  if (st != RISE_OK) return st;
+  *plan = new rise_plan{impl};
+  return RISE_OK;
+}
+
+rise_status rise_plan_launch(rise_plan* plan, void* stream) {
+  clear_error();
+  if (!plan || !plan->impl) return fail(RISE_ERR_NULL, "rise_plan_launch: plan is NULL");
+  return plan_launch(plan->impl, (hipStream_t)stream);
+}
+
+rise_status rise_plan_launch_direct(rise_plan* plan, void* stream) {
+  clear_error();
+  if (!plan || !plan->impl) return fail(RISE_ERR_NULL, "rise_plan_launch_direct: plan is NULL");
+  return plan_launch_direct(plan->impl, (hipStream_t)stream);
+}
+
+rise_status rise_plan_destroy(rise_plan* plan) {
+  clear_error();
+  if (!plan) return RISE_OK;
+  rise_plan_free(plan->impl);
+  delete plan;
+  return RISE_OK;
+}
+
+int32_t rise_plan_items(const rise_plan* plan) {
+  return plan && plan->impl ? plan_items(plan->impl) : 0;
+}
+
+rise_status rise_plan_tile(const rise_plan* plan, int32_t problem, rise_tile* tile) {
+  clear_error();
+  if (!plan || !plan->impl || !tile) return fail(RISE_ERR_NULL, "rise_plan_tile: NULL");
+  const int k = plan_kind(plan->impl, problem);
+  if (k < 0 || kind_is_stencil(k)) return fail(RISE_ERR_SHAPE, "rise_plan_tile: not a GEMM problem");
+  const char* n = kind_name(k);  // "<dtype>_<bm>x<bn>_<op>"
+  int bm = 0, bn = 0;
+  const char* us = strchr(n, '_');
+  if (!us || sscanf(us + 1, "%dx%d", &bm, &bn) != 2) return fail(RISE_ERR_HIP, "rise_plan_tile");
+  *tile = rise_tile{bm, bn, 32};
+  return RISE_OK;
+}
+
+static rise_status run_once(const rise_gemm_problem* g, int ng, const rise_stencil_problem* s,
+                            int ns, void* stream) {
+  rise_plan* plan = nullptr;
+  rise_status st = rise_plan_create(&plan, g, ng, s, ns, nullptr, stream);
+  if (st != RISE_OK) return st;
+  st = rise_plan_launch(plan, stream);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  rise_plan_destroy(plan);
+  if (st == RISE_OK && e != hipSuccess)
+    st = fail(RISE_ERR_HIP, std::string("batched: ") + hipGetErrorString(e));
+  return st;
+}
+
+rise_status rise_gemm_batched(const rise_gemm_problem* gemms, int32_t n, void* stream) {
+  return run_once(gemms, n, nullptr, 0, stream);
+}
+
+rise_status rise_stencil2d_batched(const rise_stencil_problem* stencils, int32_t n,
+                                   void* stream) {
+  return run_once(nullptr, 0, stencils, n, stream);
+}
+
+rise_status rise_autotune_batched(const char* table_path, void* stream) {
+  clear_error();
+  if (!table_path) return fail(RISE_ERR_NULL, "rise_autotune_batched: table_path is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = 4096;
+  void *A = nullptr, *B = nullptr, *C = nullptr, *w = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc(&A, (size_t)n * n * 4)) != hipSuccess || (e = hipMalloc(&B, (size_t)n * n * 4)) != hipSuccess ||
+      (e = hipMalloc(&C, (size_t)n * n * 4)) != hipSuccess || (e = hipMalloc(&w, 256)) != hipSuccess) {
+    hipFree(A); hipFree(B); hipFree(C); hipFree(w);
+    return fail(RISE_ERR_HIP, std::string("rise_autotune_batched: ") + hipGetErrorString(e));
+  }
+  hipMemsetAsync(A, 0, (size_t)n * n * 4, s);
+  hipMemsetAsync(B, 0, (size_t)n * n * 4, s);
+  hipMemsetAsync(w, 0, 256, s);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  FILE* f = fopen(table_path, "w");
+  if (!f) {
+    hipFree(A); hipFree(B); hipFree(C); hipFree(w);
+    return fail(RISE_ERR_UNSUPPORTED, "rise_autotune_batched: cannot write the table");
+  }
+  rise_status st = RISE_OK;
+  // time one plan (graph launches) and return the cost of one item slot in us:
+  // total time x concurrent workgroups / items
+  auto measure = [&](const rise_gemm_problem* g, const rise_stencil_problem* sp, int kind,
+                     double* per_item) -> rise_status {
+    PlanImpl* p = nullptr;
+    rise_status r = plan_build(&p, g, g ? 1 : 0, sp, sp ? 1 : 0, nullptr, kind, s);
+    if (r != RISE_OK) return r;
+    plan_launch(p, s);  // warm-up
+    hipEventRecord(e0, s);
+    const int reps = 5;
+    for (int i = 0; i < reps; i++) plan_launch(p, s);
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    *per_item = (double)ms * 1e3 / reps * plan_grid(p) / std::max(1, plan_items(p));
+    rise_plan_free(p);
+    return RISE_OK;
+  };
+  for (int k = 0; k < num_kinds() && st == RISE_OK; k++) {
+    if (kind_is_stencil(k)) {
+      const int side = 1 + 2 * (k - (num_kinds() - 4));
+      rise_stencil_problem sp{(float*)C, (const float*)A, (const float*)w, n, n, n, n, side,
+                              RISE_PAD_CLAMP};
+      double t = 0;
+      st = measure(nullptr, &sp, -1, &t);
+      fprintf(f, "%s %.6f %.8f\n", kind_name(k), t, 0.0);
+    } else {
+      double t1 = 0, t2 = 0;
+      const int K1 = 128, K2 = 1024;
+      rise_gemm_problem g1{(float*)C, A, B, n, n, K1, K1, kind_opb(k) ? K1 : n, n,
+                           kind_dtype(k), kind_opb(k)};
+      rise_gemm_problem g2{(float*)C, A, B, n, n, K2, K2, kind_opb(k) ? K2 : n, n,
+                           kind_dtype(k), kind_opb(k)};
+      st = measure(&g1, nullptr, k, &t1);
+      if (st == RISE_OK) st = measure(&g2, nullptr, k, &t2);
+      const double b = (t2 - t1) / (K2 - K1), a = t1 - b * K1;
+      fprintf(f, "%s %.6f %.8f\n", kind_name(k), a, b);
+    }
+  }
+  fclose(f);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(A); hipFree(B); hipFree(C); hipFree(w);
+  return st;
 }
 
 }  // extern "C"

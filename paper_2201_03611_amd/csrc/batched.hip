@@ -1,0 +1,392 @@
+// Batched form: many GEMMs and stencils of uneven sizes in one persistent launch.
+//
+// The batch is the outer map of the patterns: every (problem, output tile) pair
+// is an independent work item (distinct output acceptors, paper Sec. V-C), so
+// the items can run in any order.  The host builds a table of problem
+// descriptors and a flat list of work items sorted by estimated cost (largest
+// first), picks a tile shape for every GEMM from a measured cost table, and
+// captures  [reset counter] -> [persistent kernel]  in a HIP graph.  Every
+// persistent workgroup repeatedly takes the next item with one atomic add and
+// runs the matching tile function (tiles.h) on a shared LDS buffer, so a batch
+// costs one launch instead of one per problem.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "batched.h"
+#include "tiles.h"
+
+namespace rise {
+namespace {
+
+using tiles::kThreads;
+
+// tile kinds of the persistent kernel
+enum Kind : int {
+  F32_64x64_N, F32_64x64_T, F32_128x64_N, F32_128x64_T, F32_64x128_N, F32_64x128_T,
+  F32_128x128_N, F32_128x128_T,
+  BF16_64x64_N, BF16_64x64_T, BF16_128x128_N, BF16_128x128_T,
+  STENCIL_1, STENCIL_3, STENCIL_5, STENCIL_7,
+  NUM_KINDS
+};
+struct KindShape {
+  int bm, bn, bk;
+};
+const KindShape kShape[NUM_KINDS] = {
+    {64, 64, 32}, {64, 64, 32}, {128, 64, 32}, {128, 64, 32}, {64, 128, 32}, {64, 128, 32},
+    {128, 128, 32}, {128, 128, 32}, {64, 64, 32}, {64, 64, 32}, {128, 128, 32}, {128, 128, 32},
+    {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}};
+constexpr int kStencilRows = 16;
+
+struct Desc {  // one problem
+  float* out;
+  const void* a;   // GEMM A / stencil input
+  const void* b;   // GEMM B / stencil weights
+  int64_t lda, ldb, ldc;  // stencil: lda = ld_in, ldc = ld_out
+  int M, N, K;            // stencil: M = H, N = W, K = window side
+  int kind;
+  int tiles_n;            // tiles along N (GEMM) or along W (stencil)
+  int zero_pad;
+  int pad_;
+};
+struct Item {
+  int desc, tile;
+};
+
+constexpr int f32_lds_bytes() {
+  return 4 * tiles::F32Cfg<128, 128, 32, false, false>::LDS_FLOATS;
+}
+constexpr int kLdsBytes = f32_lds_bytes();  // the largest tile (FP32 128 x 128 x 32)
+static_assert(4 * tiles::F32Cfg<128, 128, 32, false, true>::LDS_FLOATS <= kLdsBytes, "lds");
+static_assert(16 * tiles::Bf16Cfg<128, 128, 32>::LDS_CHUNKS <= kLdsBytes, "lds");
+static_assert(16 * tiles::StencilCfg<7, kStencilRows>::LDS_CHUNKS <= kLdsBytes, "lds");
+
+__device__ __forceinline__ void run_item(const Desc& d, int tile, char* lds) {
+  const int tm = tile / d.tiles_n, tn = tile - tm * d.tiles_n;
+  float* fl = reinterpret_cast<float*>(lds);
+  i32x4* cl = reinterpret_cast<i32x4*>(lds);
+  f32x4* sl = reinterpret_cast<f32x4*>(lds);
+  const float* fa = reinterpret_cast<const float*>(d.a);
+  const float* fb = reinterpret_cast<const float*>(d.b);
+  const uint16_t* ha = reinterpret_cast<const uint16_t*>(d.a);
+  const uint16_t* hb = reinterpret_cast<const uint16_t*>(d.b);
+#define RISE_F32(BM, BN, TB)                                                                    \
+  tiles::gemm_f32_tile<BM, BN, 32, false, TB, true>(d.out, d.ldc, fa, d.lda, fb, d.ldb, d.M, d.N, \
+                                                    d.K, tm * BM, tn * BN, fl)
+#define RISE_BF16(BM, BN, TB)                                                                   \
+  tiles::gemm_bf16_tile<BM, BN, 32, TB>(d.out, d.ldc, ha, d.lda, hb, d.ldb, d.M, d.N, d.K,      \
+                                        tm * BM, tn * BN, cl)
+#define RISE_STENCIL(K)                                                                         \
+  tiles::stencil_lds_tile<K, true, kStencilRows>(d.out, d.ldc, fa, d.lda, d.M, d.N, fb,         \
+                                                 d.zero_pad, tm * kStencilRows,                \
+                                                 tn * tiles::kStencilTX, sl)
+  switch (d.kind) {
+    case F32_64x64_N: RISE_F32(64, 64, false); break;
+    case F32_64x64_T: RISE_F32(64, 64, true); break;
+    case F32_128x64_N: RISE_F32(128, 64, false); break;
+    case F32_128x64_T: RISE_F32(128, 64, true); break;
+    case F32_64x128_N: RISE_F32(64, 128, false); break;
+    case F32_64x128_T: RISE_F32(64, 128, true); break;
+    case F32_128x128_N: RISE_F32(128, 128, false); break;
+    case F32_128x128_T: RISE_F32(128, 128, true); break;
+    case BF16_64x64_N: RISE_BF16(64, 64, false); break;
+    case BF16_64x64_T: RISE_BF16(64, 64, true); break;
+    case BF16_128x128_N: RISE_BF16(128, 128, false); break;
+    case BF16_128x128_T: RISE_BF16(128, 128, true); break;
+    case STENCIL_1: RISE_STENCIL(1); break;
+    case STENCIL_3: RISE_STENCIL(3); break;
+    case STENCIL_5: RISE_STENCIL(5); break;
+    case STENCIL_7: RISE_STENCIL(7); break;
+    default: break;
+  }
+#undef RISE_F32
+#undef RISE_BF16
+#undef RISE_STENCIL
+}
+
+__global__ void reset_counter(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+// Every workgroup takes items until the list is exhausted; the exit condition
+// (item >= n_items) is reached by every workgroup because the counter only grows.
+__global__ __launch_bounds__(kThreads, 2) void batched_kernel(const Desc* __restrict__ descs,
+                                                              const Item* __restrict__ items,
+                                                              int n_items, int* counter) {
+  __shared__ __attribute__((aligned(16))) char lds[kLdsBytes];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();  // every thread has read `next` before it is overwritten
+    if (it >= n_items) break;
+    const Item item = items[it];
+    run_item(descs[item.desc], item.tile, lds);
+    __syncthreads();  // the LDS buffer is free for the next item
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+// Cost model of one tile: a + b * K microseconds (GEMM), a (stencil); measured
+// per kind by rise_autotune_batched and read from its table.  The built-in
+// values below were measured on an MI355X with that routine.
+struct Cost {
+  double a, b;
+};
+Cost g_default_cost[NUM_KINDS] = {
+    {1.0, 0.0040}, {1.0, 0.0042}, {1.2, 0.0068}, {1.2, 0.0070}, {1.2, 0.0068}, {1.2, 0.0070},
+    {1.5, 0.0125}, {1.5, 0.0128}, {1.0, 0.0014}, {1.0, 0.0016}, {1.5, 0.0040}, {1.5, 0.0044},
+    {1.0, 0.0},    {1.5, 0.0},    {2.0, 0.0},    {2.5, 0.0}};
+
+const char* kKindNames[NUM_KINDS] = {
+    "f32_64x64_N", "f32_64x64_T", "f32_128x64_N", "f32_128x64_T", "f32_64x128_N",
+    "f32_64x128_T", "f32_128x128_N", "f32_128x128_T", "bf16_64x64_N", "bf16_64x64_T",
+    "bf16_128x128_N", "bf16_128x128_T", "stencil_1", "stencil_3", "stencil_5", "stencil_7"};
+
+bool load_costs(const char* path, Cost* cost) {
+  for (int k = 0; k < NUM_KINDS; k++) cost[k] = g_default_cost[k];
+  if (!path) return true;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char name[64];
+  double a, b;
+  while (fscanf(f, "%63s %lf %lf", name, &a, &b) == 3) {
+    for (int k = 0; k < NUM_KINDS; k++)
+      if (std::string(name) == kKindNames[k]) cost[k] = Cost{a, b};
+  }
+  fclose(f);
+  return true;
+}
+
+int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+double gemm_cost(const Cost* cost, int kind, int M, int N, int K) {
+  const KindShape& s = kShape[kind];
+  return (double)ceil_div(M, s.bm) * ceil_div(N, s.bn) * (cost[kind].a + cost[kind].b * K);
+}
+
+int pick_gemm_kind(const Cost* cost, int dtype, int opB, int M, int N, int K, int forced) {
+  if (forced >= 0) return forced;
+  const int t = opB == RISE_OP_T ? 1 : 0;
+  int best = -1;
+  double best_c = 0;
+  const int first = dtype == RISE_F32 ? F32_64x64_N : BF16_64x64_N;
+  const int last = dtype == RISE_F32 ? F32_128x128_T : BF16_128x128_T;
+  for (int k = first + t; k <= last; k += 2) {
+    double c = gemm_cost(cost, k, M, N, K);
+    if (best < 0 || c < best_c) best = k, best_c = c;
+  }
+  return best;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+rise_status check_gemm_problem(const rise_gemm_problem& p, int i) {
+  auto where = [&](const char* w) { return std::string("batched gemm ") + std::to_string(i) + ": " + w; };
+  if (p.M < 0 || p.N < 0 || p.K < 0 || p.M >= (1LL << 31) || p.N >= (1LL << 31) || p.K >= (1LL << 31))
+    return fail(RISE_ERR_SHAPE, where("sizes"));
+  if (p.dtype != RISE_F32 && p.dtype != RISE_BF16) return fail(RISE_ERR_DTYPE, where("dtype"));
+  if (p.opB != RISE_OP_N && p.opB != RISE_OP_T) return fail(RISE_ERR_UNSUPPORTED, where("opB"));
+  if (p.M == 0 || p.N == 0) return RISE_OK;
+  if (!p.C || (p.K > 0 && (!p.A || !p.B))) return fail(RISE_ERR_NULL, where("NULL pointer"));
+  const int64_t bc = p.opB == RISE_OP_N ? p.N : p.K;
+  if (p.ldc < p.N || (p.K > 0 && (p.lda < p.K || p.ldb < bc))) return fail(RISE_ERR_SHAPE, where("ld"));
+  const int q = p.dtype == RISE_F32 ? 4 : 8;  // elements per 16 bytes
+  if (p.K > 0 && (!aligned16(p.A) || !aligned16(p.B) || p.lda % q || p.ldb % q))
+    return fail(RISE_ERR_UNSUPPORTED, where("A, B must be 16-byte aligned with lda, ldb multiples "
+                                            "of 16 bytes"));
+  if (p.dtype == RISE_BF16 && (p.K % 8 || (p.opB == RISE_OP_N && p.N % 8)))
+    return fail(RISE_ERR_UNSUPPORTED, where("bf16 needs K (and N when B is K x N) multiples of 8"));
+  const int64_t esz = p.dtype == RISE_F32 ? 4 : 2;
+  auto span = [](const void* ptr, int64_t rows, int64_t cols, int64_t ld, int64_t e) {
+    uintptr_t lo = (uintptr_t)ptr;
+    return std::make_pair(lo, lo + (uintptr_t)(((rows - 1) * ld + cols) * e));
+  };
+  auto rc = span(p.C, p.M, p.N, p.ldc, 4);
+  if (p.K > 0) {
+    auto ra = span(p.A, p.M, p.K, p.lda, esz);
+    auto rb = span(p.B, p.opB == RISE_OP_N ? p.K : p.N, bc, p.ldb, esz);
+    auto ov = [](std::pair<uintptr_t, uintptr_t> x, std::pair<uintptr_t, uintptr_t> y) {
+      return x.first < y.second && y.first < x.second;
+    };
+    if (ov(rc, ra) || ov(rc, rb)) return fail(RISE_ERR_ALIAS, where("C overlaps A or B"));
+  }
+  return RISE_OK;
+}
+
+rise_status check_stencil_problem(const rise_stencil_problem& p, int i) {
+  auto where = [&](const char* w) { return std::string("batched stencil ") + std::to_string(i) + ": " + w; };
+  if (p.H < 0 || p.W < 0 || p.H >= (1LL << 31) || p.W >= (1LL << 31))
+    return fail(RISE_ERR_SHAPE, where("sizes"));
+  if (p.k != 1 && p.k != 3 && p.k != 5 && p.k != 7)
+    return fail(RISE_ERR_UNSUPPORTED, where("window side must be 1, 3, 5 or 7"));
+  if (p.pad != RISE_PAD_CLAMP && p.pad != RISE_PAD_ZERO) return fail(RISE_ERR_UNSUPPORTED, where("pad"));
+  if (p.H == 0 || p.W == 0) return RISE_OK;
+  if (!p.out || !p.in || !p.w) return fail(RISE_ERR_NULL, where("NULL pointer"));
+  if (p.ld_in < p.W || p.ld_out < p.W) return fail(RISE_ERR_SHAPE, where("ld"));
+  if (!aligned16(p.in) || !aligned16(p.out) || p.ld_in % 4 || p.ld_out % 4)
+    return fail(RISE_ERR_UNSUPPORTED, where("images must be 16-byte aligned, ld multiples of 4"));
+  uintptr_t olo = (uintptr_t)p.out, ohi = olo + (uintptr_t)(((p.H - 1) * p.ld_out + p.W) * 4);
+  uintptr_t ilo = (uintptr_t)p.in, ihi = ilo + (uintptr_t)(((p.H - 1) * p.ld_in + p.W) * 4);
+  uintptr_t wlo = (uintptr_t)p.w, whi = wlo + (uintptr_t)(p.k * p.k * 4);
+  if ((olo < ihi && ilo < ohi) || (olo < whi && wlo < ohi))
+    return fail(RISE_ERR_ALIAS, where("out overlaps in or w"));
+  return RISE_OK;
+}
+
+}  // namespace
+
+struct PlanImpl {
+  Desc* d_desc = nullptr;
+  Item* d_items = nullptr;
+  int* d_counter = nullptr;
+  int n_items = 0, grid = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> kinds;  // chosen kind per problem (GEMMs first, then stencils)
+  double est_us = 0;
+};
+
+rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
+                       const rise_stencil_problem* st, int ns, const char* tune_path,
+                       int forced_kind, hipStream_t stream) {
+  *out = nullptr;
+  if (ng < 0 || ns < 0) return fail(RISE_ERR_SHAPE, "rise_plan_create: negative count");
+  if ((ng > 0 && !g) || (ns > 0 && !st)) return fail(RISE_ERR_NULL, "rise_plan_create: NULL list");
+  for (int i = 0; i < ng; i++) {
+    rise_status s = check_gemm_problem(g[i], i);
+    if (s != RISE_OK) return s;
+  }
+  for (int i = 0; i < ns; i++) {
+    rise_status s = check_stencil_problem(st[i], i);
+    if (s != RISE_OK) return s;
+  }
+  Cost cost[NUM_KINDS];
+  if (!load_costs(tune_path, cost)) return fail(RISE_ERR_UNSUPPORTED, "rise_plan_create: cannot read tune table");
+
+  std::vector<Desc> descs;
+  std::vector<double> unit;  // estimated microseconds per tile of each problem
+  std::vector<int> ntile;
+  auto plan = new PlanImpl();
+  for (int i = 0; i < ng; i++) {
+    const rise_gemm_problem& p = g[i];
+    const int kind = pick_gemm_kind(cost, p.dtype, p.opB, (int)p.M, (int)p.N, (int)p.K,
+                                    forced_kind);
+    plan->kinds.push_back(kind);
+    const KindShape& s = kShape[kind];
+    Desc d{p.C, p.A, p.B, p.lda, p.ldb, p.ldc, (int)p.M, (int)p.N, (int)p.K, kind,
+           ceil_div(p.N, s.bn), 0, 0};
+    descs.push_back(d);
+    ntile.push_back((p.M == 0 || p.N == 0) ? 0 : ceil_div(p.M, s.bm) * d.tiles_n);
+    unit.push_back(cost[kind].a + cost[kind].b * p.K);
+  }
+  for (int i = 0; i < ns; i++) {
+    const rise_stencil_problem& p = st[i];
+    const int kind = STENCIL_1 + (p.k - 1) / 2;
+    plan->kinds.push_back(kind);
+    Desc d{p.out, p.in, p.w, p.ld_in, 0, p.ld_out, (int)p.H, (int)p.W, p.k, kind,
+           ceil_div(p.W, tiles::kStencilTX), p.pad == RISE_PAD_ZERO, 0};
+    descs.push_back(d);
+    ntile.push_back((p.H == 0 || p.W == 0) ? 0 : ceil_div(p.H, kStencilRows) * d.tiles_n);
+    unit.push_back(cost[kind].a);
+  }
+  // largest tiles first (longest-processing-time order): the tail of the launch
+  // is made of the cheapest items
+  std::vector<int> order(descs.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return unit[x] > unit[y]; });
+  std::vector<Item> items;
+  for (int d : order) {
+    plan->est_us += unit[d] * ntile[d];
+    for (int t = 0; t < ntile[d]; t++) items.push_back(Item{d, t});
+  }
+  plan->n_items = (int)items.size();
+
+  int dev = 0, cus = 256;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  plan->grid = std::max(1, std::min(plan->n_items, 2 * cus));
+
+  hipError_t e = hipSuccess;
+  const size_t nd = std::max<size_t>(descs.size(), 1), ni = std::max<size_t>(items.size(), 1);
+  if ((e = hipMalloc(&plan->d_desc, nd * sizeof(Desc))) != hipSuccess ||
+      (e = hipMalloc(&plan->d_items, ni * sizeof(Item))) != hipSuccess ||
+      (e = hipMalloc(&plan->d_counter, 256)) != hipSuccess) {
+    rise_plan_free(plan);
+    return fail(RISE_ERR_HIP, std::string("rise_plan_create: ") + hipGetErrorString(e));
+  }
+  if ((!descs.empty() &&
+       (e = hipMemcpy(plan->d_desc, descs.data(), descs.size() * sizeof(Desc), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (!items.empty() &&
+       (e = hipMemcpy(plan->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)) {
+    rise_plan_free(plan);
+    return fail(RISE_ERR_HIP, std::string("rise_plan_create: ") + hipGetErrorString(e));
+  }
+  // capture [reset counter] -> [persistent kernel] on a private stream
+  hipStream_t cap;
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) {
+    rise_plan_free(plan);
+    return fail(RISE_ERR_HIP, std::string("rise_plan_create: ") + hipGetErrorString(e));
+  }
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, cap, plan->d_counter);
+    if (plan->n_items > 0)
+      hipLaunchKernelGGL(batched_kernel, dim3(plan->grid), dim3(kThreads), 0, cap, plan->d_desc,
+                         plan->d_items, plan->n_items, plan->d_counter);
+    e = hipStreamEndCapture(cap, &plan->graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+  hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    rise_plan_free(plan);
+    return fail(RISE_ERR_HIP, std::string("rise_plan_create: graph: ") + hipGetErrorString(e));
+  }
+  (void)stream;
+  *out = plan;
+  return RISE_OK;
+}
+
+rise_status plan_launch(PlanImpl* p, hipStream_t s) {
+  hipError_t e = hipGraphLaunch(p->exec, s);
+  if (e != hipSuccess) return fail(RISE_ERR_HIP, std::string("rise_plan_launch: ") + hipGetErrorString(e));
+  return RISE_OK;
+}
+
+rise_status plan_launch_direct(PlanImpl* p, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, p->d_counter);
+  if (p->n_items > 0)
+    hipLaunchKernelGGL(batched_kernel, dim3(p->grid), dim3(kThreads), 0, s, p->d_desc, p->d_items,
+                       p->n_items, p->d_counter);
+  return check_launch("batched_kernel");
+}
+
+void rise_plan_free(PlanImpl* p) {
+  if (!p) return;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->d_desc) hipFree(p->d_desc);
+  if (p->d_items) hipFree(p->d_items);
+  if (p->d_counter) hipFree(p->d_counter);
+  delete p;
+}
+
+int plan_items(const PlanImpl* p) { return p->n_items; }
+int plan_grid(const PlanImpl* p) { return p->grid; }
+double plan_estimate(const PlanImpl* p) { return p->est_us; }
+int plan_kind(const PlanImpl* p, int i) { return i >= 0 && i < (int)p->kinds.size() ? p->kinds[i] : -1; }
+const char* kind_name(int k) { return k >= 0 && k < NUM_KINDS ? kKindNames[k] : ""; }
+int num_kinds() { return NUM_KINDS; }
+int kind_is_stencil(int k) { return k >= STENCIL_1; }
+int kind_dtype(int k) { return k >= BF16_64x64_N && k <= BF16_128x128_T ? RISE_BF16 : RISE_F32; }
+int kind_opb(int k) { return k < STENCIL_1 ? (k & 1) : -1; }
+
+}  // namespace rise

@@ -21,128 +21,23 @@
 // sums in the same order).  Square windows of 1, 3, 5 and 7 use these
 // kernels; other odd sizes up to 15 use a direct per-output kernel.
 #include "common.h"
+#include "tiles.h"
 
 namespace rise {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int TX = 256;            // columns per workgroup / wave strip (64 lanes x 4)
-constexpr int HALO = 4;            // LDS columns left and right of the tile
-constexpr int LCOLS = TX + 2 * HALO;
-constexpr int LCHUNKS = LCOLS / 4;  // 16-byte chunks per LDS row
-
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+using tiles::clampi;
+using tiles::kThreads;
+constexpr int TX = tiles::kStencilTX;  // columns per workgroup / wave strip (64 lanes x 4)
 
 template <int K, bool VEC, int TY>
 __global__ __launch_bounds__(kThreads) void stencil2d_tiled(
     float* __restrict__ out, int64_t ld_out, const float* __restrict__ in, int64_t ld_in, int H,
     int W, const float* __restrict__ w, int zero_pad, int tiles_x) {
-  constexpr int R = (K - 1) / 2;
-  constexpr int RW = TY / 4;  // output rows per wave
-  constexpr int ROWS = TY + 2 * R;
-  constexpr int TOTAL = ROWS * LCHUNKS;
-  constexpr int PER = (TOTAL + kThreads - 1) / kThreads;
-  __shared__ f32x4 tile[ROWS][LCHUNKS];
-
-  const int tid = threadIdx.x;
-  int lid = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int y0 = (lid / tiles_x) * TY;
-  const int x0 = (lid % tiles_x) * TX;
-
-  // ---- halo tile: global -> registers -> LDS ------------------------------
-  f32x4 st[PER];
-#pragma unroll
-  for (int p = 0; p < PER; p++) {
-    const int c = tid + p * kThreads;
-    f32x4 v = {0.f, 0.f, 0.f, 0.f};
-    if (c < TOTAL) {
-      const int lr = c / LCHUNKS, cc = c - lr * LCHUNKS;
-      int gy = y0 - R + lr;
-      const int gx = x0 - HALO + cc * 4;
-      bool row_ok = true;
-      if (gy < 0 || gy >= H) {
-        if (zero_pad) row_ok = false;
-        gy = clampi(gy, 0, H - 1);
-      }
-      if (row_ok) {
-        const float* rp = in + (int64_t)gy * ld_in;
-        if (VEC && gx >= 0 && gx + 3 < W) {
-          v = *reinterpret_cast<const f32x4*>(rp + gx);
-        } else {
-          float e[4];
-#pragma unroll
-          for (int q = 0; q < 4; q++) {
-            int xx = gx + q;
-            if (xx < 0 || xx >= W) {
-              e[q] = zero_pad ? 0.f : rp[clampi(xx, 0, W - 1)];
-            } else {
-              e[q] = rp[xx];
-            }
-          }
-          v = f32x4{e[0], e[1], e[2], e[3]};
-        }
-      }
-    }
-    st[p] = v;
-  }
-#pragma unroll
-  for (int p = 0; p < PER; p++) {
-    const int c = tid + p * kThreads;
-    if (c < TOTAL) {
-      const int lr = c / LCHUNKS;
-      tile[lr][c - lr * LCHUNKS] = st[p];
-    }
-  }
-  __syncthreads();
-
-  // ---- weights (uniform: scalar loads) -----------------------------------
-  float wt[K][K];
-#pragma unroll
-  for (int dy = 0; dy < K; dy++)
-#pragma unroll
-    for (int dx = 0; dx < K; dx++) wt[dy][dx] = w[dy * K + dx];
-
-  // ---- windows and weighted reduce ----------------------------------------
-  const int lane = tid & 63, wave = tid >> 6;
-  const int r0 = wave * RW;  // first output row of this wave (tile-local)
-  // lane's chunks: LDS chunk `lane` = columns x-4..x-1, lane+1 = x..x+3, lane+2 = x+4..x+7
-  float win[RW + 2 * R][12];
-#pragma unroll
-  for (int j = 0; j < RW + 2 * R; j++) {
-    f32x4 c1 = tile[r0 + j][lane + 1];
-    win[j][4] = c1.x; win[j][5] = c1.y; win[j][6] = c1.z; win[j][7] = c1.w;
-    if (R > 0) {
-      f32x4 c0 = tile[r0 + j][lane];
-      f32x4 c2 = tile[r0 + j][lane + 2];
-      win[j][0] = c0.x; win[j][1] = c0.y; win[j][2] = c0.z; win[j][3] = c0.w;
-      win[j][8] = c2.x; win[j][9] = c2.y; win[j][10] = c2.z; win[j][11] = c2.w;
-    }
-  }
-  const int x = x0 + lane * 4;
-#pragma unroll
-  for (int o = 0; o < RW; o++) {
-    float acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      float a = 0.f;
-#pragma unroll
-      for (int dy = 0; dy < K; dy++)
-#pragma unroll
-        for (int dx = 0; dx < K; dx++) a = fmaf(win[o + dy][4 + q + dx - R], wt[dy][dx], a);
-      acc[q] = a;
-    }
-    const int y = y0 + r0 + o;
-    if (y < H) {
-      float* op = out + (int64_t)y * ld_out;
-      if (VEC && x + 3 < W) {
-        *reinterpret_cast<f32x4*>(op + x) = f32x4{acc[0], acc[1], acc[2], acc[3]};
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-          if (x + q < W) op[x + q] = acc[q];
-      }
-    }
-  }
+  __shared__ f32x4 lds[tiles::StencilCfg<K, TY>::LDS_CHUNKS];
+  const int lid = xcd_contiguous(blockIdx.x, gridDim.x);
+  tiles::stencil_lds_tile<K, VEC, TY>(out, ld_out, in, ld_in, H, W, w, zero_pad,
+                                      (lid / tiles_x) * TY, (lid % tiles_x) * TX, lds);
 }
 
 // Streaming schedule: every wave owns one 256-column strip segment of `L`

@@ -1,0 +1,460 @@
+// Tile-level device functions shared by the one-problem kernels and the
+// persistent batched kernel.  Each function computes one output tile with the
+// whole 256-thread workgroup and takes its LDS through a pointer, so a kernel
+// that runs several kinds of tiles can overlay them in one buffer.
+#pragma once
+
+#include "common.h"
+
+namespace rise {
+namespace tiles {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// ===========================================================================
+// FP32 GEMM tile (v_mfma_f32_32x32x2_f32): C[m0:m0+BM, n0:n0+BN] = A B
+// ===========================================================================
+template <int BM, int BN, int BK, bool TA, bool TB>
+struct F32Cfg {
+  // LDS layout: k-major slabs, [BK][BM + pad] and [BK][BN + pad], double buffered.
+  // Transposing writes (operand stored K-contiguous) use an odd pad so that the
+  // scalar writes of a half-wave hit distinct banks; direct float4 writes use
+  // pad 4 to keep rows 16-byte aligned.
+  static constexpr int PA = TA ? 4 : 1;
+  static constexpr int PB = TB ? 1 : 4;
+  static constexpr int LA = BM + PA;
+  static constexpr int LB = BN + PB;
+  static constexpr int NA = BM * BK / 4 / kThreads;  // float4 chunks per thread
+  static constexpr int NB = BN * BK / 4 / kThreads;
+  static constexpr int LDS_FLOATS = 2 * BK * (LA + LB);
+  static_assert(NA >= 1 && NB >= 1, "tile too small for 256 threads");
+  static_assert(BM * BK / 4 % kThreads == 0 && BN * BK / 4 % kThreads == 0, "tile split");
+};
+
+__device__ __forceinline__ f32x4 load4_guarded(const float* p, int valid) {
+  // valid = number of in-bounds elements (<= 4) along the contiguous direction
+  f32x4 v = {0.f, 0.f, 0.f, 0.f};
+  if (valid > 0) v.x = p[0];
+  if (valid > 1) v.y = p[1];
+  if (valid > 2) v.z = p[2];
+  if (valid > 3) v.w = p[3];
+  return v;
+}
+
+template <bool VEC>
+__device__ __forceinline__ f32x4 load_chunk(const float* base, int64_t row_off, int col,
+                                            bool row_ok, int cols) {
+  // 4 consecutive elements from base[row_off + col]; out-of-range elements read 0
+  if (!row_ok) return f32x4{0.f, 0.f, 0.f, 0.f};
+  const float* p = base + row_off + col;
+  const int valid = cols - col;
+  if (VEC && valid >= 4) return *reinterpret_cast<const f32x4*>(p);
+  return load4_guarded(p, valid > 4 ? 4 : valid);
+}
+
+// Pattern -> hardware mapping (paper Sec. IV-B/C: splitJoinMap, the map lowerings
+// and fuseReduceMap; Sec. V-C: toMem and reduceSeq): the workgroup owns one
+// split(BM) x split(BN) tile (mapWorkGroup); its 2 x 2 sub-tiles go to the four
+// waves (mapLocal); split(BK) + reduceSeq(Private) is the K loop with register
+// accumulators; each slab is staged in LDS (toMem(Local)), double buffered so the
+// global fetch of slab i+1 is in flight while the matrix cores consume slab i;
+// zip |> map(*) |> reduce(+) is v_mfma_f32_32x32x2_f32; join . join is the
+// guarded row-major store.  Operands may be read through transpose (TA, TB)
+// without copies.  Ragged M/N/K: guarded loads supply zeros (exact for the
+// sum), stores are guarded.
+template <int BM, int BN, int BK, bool TA, bool TB, bool VEC>
+__device__ __forceinline__ void gemm_f32_tile(float* __restrict__ C, int64_t ldc,
+                                              const float* __restrict__ A, int64_t lda,
+                                              const float* __restrict__ B, int64_t ldb, int M,
+                                              int N, int K, int m0, int n0, float* lds) {
+  using T = F32Cfg<BM, BN, BK, TA, TB>;
+  constexpr int WM = BM / 2, WN = BN / 2;  // wave tile (2 x 2 waves)
+  constexpr int TM = WM / 32, TN = WN / 32;
+  static_assert(TM >= 1 && TN >= 1, "wave tile below one 32x32 block");
+  auto As = reinterpret_cast<float(*)[BK][T::LA]>(lds);
+  auto Bs = reinterpret_cast<float(*)[BK][T::LB]>(lds + 2 * BK * T::LA);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM;
+  const int wn0 = (wave & 1) * WN;
+
+  f32x4 ra[T::NA], rb[T::NB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < T::NA; p++) {
+      int c = tid + kThreads * p;
+      if (!TA) {  // stored M x K, K contiguous
+        int row = c / (BK / 4), kc = (c % (BK / 4)) * 4;
+        ra[p] = load_chunk<VEC>(A, (int64_t)(m0 + row) * lda, k0 + kc, m0 + row < M, K);
+      } else {  // stored K x M, M contiguous
+        int k = c / (BM / 4), mc = (c % (BM / 4)) * 4;
+        ra[p] = load_chunk<VEC>(A, (int64_t)(k0 + k) * lda, m0 + mc, k0 + k < K, M);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < T::NB; p++) {
+      int c = tid + kThreads * p;
+      if (!TB) {  // stored K x N, N contiguous
+        int k = c / (BN / 4), nc = (c % (BN / 4)) * 4;
+        rb[p] = load_chunk<VEC>(B, (int64_t)(k0 + k) * ldb, n0 + nc, k0 + k < K, N);
+      } else {  // stored N x K, K contiguous
+        int n = c / (BK / 4), kc = (c % (BK / 4)) * 4;
+        rb[p] = load_chunk<VEC>(B, (int64_t)(n0 + n) * ldb, k0 + kc, n0 + n < N, K);
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < T::NA; p++) {
+      int c = tid + kThreads * p;
+      if (!TA) {
+        int row = c / (BK / 4), kc = (c % (BK / 4)) * 4;
+        As[buf][kc + 0][row] = ra[p].x;
+        As[buf][kc + 1][row] = ra[p].y;
+        As[buf][kc + 2][row] = ra[p].z;
+        As[buf][kc + 3][row] = ra[p].w;
+      } else {
+        int k = c / (BM / 4), mc = (c % (BM / 4)) * 4;
+        *reinterpret_cast<f32x4*>(&As[buf][k][mc]) = ra[p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < T::NB; p++) {
+      int c = tid + kThreads * p;
+      if (!TB) {
+        int k = c / (BN / 4), nc = (c % (BN / 4)) * 4;
+        *reinterpret_cast<f32x4*>(&Bs[buf][k][nc]) = rb[p];
+      } else {
+        int n = c / (BK / 4), kc = (c % (BK / 4)) * 4;
+        Bs[buf][kc + 0][n] = rb[p].x;
+        Bs[buf][kc + 1][n] = rb[p].y;
+        Bs[buf][kc + 2][n] = rb[p].z;
+        Bs[buf][kc + 3][n] = rb[p].w;
+      }
+    }
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  const int nk = (K + BK - 1) / BK;
+  if (nk > 0) {
+    fetch(0);
+    stash(0);
+    __syncthreads();
+  }
+  const int kl = lane >> 5;  // which k of the pair this lane supplies
+  const int il = lane & 31;  // row of A / column of B this lane supplies
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) fetch((kt + 1) * BK);  // in flight while the slab below is consumed
+#pragma unroll
+    for (int s = 0; s < BK / 2; s++) {
+      float a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; i++) a[i] = As[cur][2 * s + kl][wm0 + i * 32 + il];
+#pragma unroll
+      for (int j = 0; j < TN; j++) b[j] = Bs[cur][2 * s + kl][wn0 + j * 32 + il];
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
+  }
+
+  // D layout of a 32x32 block: lane l holds column l % 32 and rows
+  // 8*(r/4) + 4*(l/32) + r%4 for r = 0..15
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+      const int col = n0 + wn0 + j * 32 + il;
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * kl + (r & 3);
+        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// ===========================================================================
+// BF16 GEMM tile for bf16-stored operands (v_mfma_f32_32x32x16_bf16, FP32
+// accumulation): A is M x K row-major; B is either N x K (TB, K contiguous, read
+// directly) or K x N (read through transpose: each 8-element chunk along N is
+// scattered into the K-contiguous LDS layout).  Requires lda, ldb multiples of 8
+// and 16-byte aligned bases; K ragged in units of 8 (zero-filled chunks).
+// ===========================================================================
+template <int BM, int BN, int BK>
+struct Bf16Cfg {
+  static constexpr int CH = BK / 8;  // 16-byte chunks per slab row
+  static constexpr int LDS_CHUNKS = 2 * (BM + BN) * CH;
+};
+
+template <int CH>
+__device__ __forceinline__ int swz16(int r, int c) {
+  constexpr int per = 8 / CH;  // rows sharing one 128-byte bank line
+  return r * CH + (c ^ ((r / per) % CH));
+}
+
+template <int BM, int BN, int BK, bool TB>
+__device__ __forceinline__ void gemm_bf16_tile(float* __restrict__ C, int64_t ldc,
+                                               const uint16_t* __restrict__ A, int64_t lda,
+                                               const uint16_t* __restrict__ B, int64_t ldb, int M,
+                                               int N, int K, int m0, int n0, i32x4* lds) {
+  using T = Bf16Cfg<BM, BN, BK>;
+  constexpr int CH = T::CH;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
+  constexpr int LA = BM * CH / kThreads;                // A chunks per thread
+  constexpr int LB = BN * CH / kThreads;                // B chunks per thread (both layouts)
+  static_assert(LA >= 1 && LB >= 1 && TM >= 1 && TN >= 1, "tile");
+  i32x4* As = lds;
+  i32x4* Bs = lds + 2 * BM * CH;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+  const int il = lane & 31, kh = lane >> 5;
+
+  i32x4 ra[LA], rb[LB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < LA; q++) {
+      const int c = tid + kThreads * q, r = c / CH, ch = c % CH;
+      const int k = k0 + ch * 8;
+      ra[q] = (m0 + r < M && k < K)
+                  ? *reinterpret_cast<const i32x4*>(A + (int64_t)(m0 + r) * lda + k)
+                  : i32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < LB; q++) {
+      const int c = tid + kThreads * q;
+      if (TB) {  // B stored N x K
+        const int r = c / CH, ch = c % CH, k = k0 + ch * 8;
+        rb[q] = (n0 + r < N && k < K)
+                    ? *reinterpret_cast<const i32x4*>(B + (int64_t)(n0 + r) * ldb + k)
+                    : i32x4{0, 0, 0, 0};
+      } else {  // B stored K x N: chunk = 8 consecutive n at one k
+        const int k = c / (BN / 8), nc = (c % (BN / 8)) * 8;
+        rb[q] = (k0 + k < K && n0 + nc < N)
+                    ? *reinterpret_cast<const i32x4*>(B + (int64_t)(k0 + k) * ldb + n0 + nc)
+                    : i32x4{0, 0, 0, 0};
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < LA; q++) {
+      const int c = tid + kThreads * q;
+      As[buf * BM * CH + swz16<CH>(c / CH, c % CH)] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LB; q++) {
+      const int c = tid + kThreads * q;
+      if (TB) {
+        Bs[buf * BN * CH + swz16<CH>(c / CH, c % CH)] = rb[q];
+      } else {
+        const int k = c / (BN / 8), nc = (c % (BN / 8)) * 8;
+        uint16_t* bs = reinterpret_cast<uint16_t*>(Bs + buf * BN * CH);
+        const uint16_t* e = reinterpret_cast<const uint16_t*>(&rb[q]);
+#pragma unroll
+        for (int t = 0; t < 8; t++) bs[swz16<CH>(nc + t, k / 8) * 8 + (k % 8)] = e[t];
+      }
+    }
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  const int nk = (K + BK - 1) / BK;
+  if (nk > 0) {
+    fetch(0);
+    stash(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) fetch((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ks++) {
+      const int c = 2 * ks + kh;
+      bf16x8 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+        a[i] = __builtin_bit_cast(bf16x8, As[cur * BM * CH + swz16<CH>(wm0 + 32 * i + il, c)]);
+#pragma unroll
+      for (int j = 0; j < TN; j++)
+        b[j] = __builtin_bit_cast(bf16x8, Bs[cur * BN * CH + swz16<CH>(wn0 + 32 * j + il, c)]);
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+      const int col = n0 + wn0 + j * 32 + il;
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// ===========================================================================
+// Stencil tile, LDS halo schedule: out rows [y0, y0+TY) x columns [x0, x0+256)
+//   pad2D (clamp/zero)     -> index remapping while the halo tile is fetched;
+//   slide2D                -> one (TY + 2R) x (256 + 8) halo tile staged in LDS
+//                             (toMem(Local), paper Sec. V-B/C) with coalesced
+//                             16-byte loads;
+//   map(map(...))          -> each lane owns 4 adjacent outputs of a row and walks
+//                             down TY / 4 rows, keeping the k rows of its window
+//                             in registers;
+//   zip |> map(*) |> reduce -> k*k FMAs per output (fuseReduceMap, Sec. IV-B),
+//                             weights in scalar registers;
+//   join                   -> 16-byte coalesced stores.
+// ===========================================================================
+constexpr int kStencilTX = 256;   // columns per tile (64 lanes x 4)
+constexpr int kHalo = 4;          // LDS columns left and right of the tile
+constexpr int kLChunks = (kStencilTX + 2 * kHalo) / 4;  // 16-byte chunks per LDS row
+
+template <int K, int TY>
+struct StencilCfg {
+  static constexpr int R = (K - 1) / 2;
+  static constexpr int ROWS = TY + 2 * R;
+  static constexpr int LDS_CHUNKS = ROWS * kLChunks;
+};
+
+template <int K, bool VEC, int TY>
+__device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_t ld_out,
+                                                 const float* __restrict__ in, int64_t ld_in,
+                                                 int H, int W, const float* __restrict__ w,
+                                                 int zero_pad, int y0, int x0, f32x4* lds) {
+  constexpr int R = (K - 1) / 2;
+  constexpr int RW = TY / 4;  // output rows per wave
+  constexpr int ROWS = TY + 2 * R;
+  constexpr int TOTAL = ROWS * kLChunks;
+  constexpr int PER = (TOTAL + kThreads - 1) / kThreads;
+  auto tile = reinterpret_cast<f32x4(*)[kLChunks]>(lds);
+  const int tid = threadIdx.x;
+
+  f32x4 st[PER];
+#pragma unroll
+  for (int p = 0; p < PER; p++) {
+    const int c = tid + p * kThreads;
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (c < TOTAL) {
+      const int lr = c / kLChunks, cc = c - lr * kLChunks;
+      int gy = y0 - R + lr;
+      const int gx = x0 - kHalo + cc * 4;
+      bool row_ok = true;
+      if (gy < 0 || gy >= H) {
+        if (zero_pad) row_ok = false;
+        gy = clampi(gy, 0, H - 1);
+      }
+      if (row_ok) {
+        const float* rp = in + (int64_t)gy * ld_in;
+        if (VEC && gx >= 0 && gx + 3 < W) {
+          v = *reinterpret_cast<const f32x4*>(rp + gx);
+        } else {
+          float e[4];
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            const int xx = gx + q;
+            if (xx < 0 || xx >= W)
+              e[q] = zero_pad ? 0.f : rp[clampi(xx, 0, W - 1)];
+            else
+              e[q] = rp[xx];
+          }
+          v = f32x4{e[0], e[1], e[2], e[3]};
+        }
+      }
+    }
+    st[p] = v;
+  }
+#pragma unroll
+  for (int p = 0; p < PER; p++) {
+    const int c = tid + p * kThreads;
+    if (c < TOTAL) {
+      const int lr = c / kLChunks;
+      tile[lr][c - lr * kLChunks] = st[p];
+    }
+  }
+  __syncthreads();
+
+  float wt[K][K];
+#pragma unroll
+  for (int dy = 0; dy < K; dy++)
+#pragma unroll
+    for (int dx = 0; dx < K; dx++) wt[dy][dx] = w[dy * K + dx];
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int r0 = wave * RW;
+  // LDS chunk `lane` = columns x-4..x-1, lane+1 = x..x+3, lane+2 = x+4..x+7
+  float win[RW + 2 * R][12];
+#pragma unroll
+  for (int j = 0; j < RW + 2 * R; j++) {
+    f32x4 c1 = tile[r0 + j][lane + 1];
+    win[j][4] = c1.x; win[j][5] = c1.y; win[j][6] = c1.z; win[j][7] = c1.w;
+    if (R > 0) {
+      f32x4 c0 = tile[r0 + j][lane];
+      f32x4 c2 = tile[r0 + j][lane + 2];
+      win[j][0] = c0.x; win[j][1] = c0.y; win[j][2] = c0.z; win[j][3] = c0.w;
+      win[j][8] = c2.x; win[j][9] = c2.y; win[j][10] = c2.z; win[j][11] = c2.w;
+    }
+  }
+  const int x = x0 + lane * 4;
+#pragma unroll
+  for (int o = 0; o < RW; o++) {
+    float acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      float a = 0.f;
+#pragma unroll
+      for (int dy = 0; dy < K; dy++)
+#pragma unroll
+        for (int dx = 0; dx < K; dx++) a = fmaf(win[o + dy][4 + q + dx - R], wt[dy][dx], a);
+      acc[q] = a;
+    }
+    const int y = y0 + r0 + o;
+    if (y < H) {
+      float* op = out + (int64_t)y * ld_out;
+      if (VEC && x + 3 < W) {
+        *reinterpret_cast<f32x4*>(op + x) = f32x4{acc[0], acc[1], acc[2], acc[3]};
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          if (x + q < W) op[x + q] = acc[q];
+      }
+    }
+  }
+}
+
+}  // namespace tiles
+}  // namespace rise

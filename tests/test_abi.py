@@ -165,3 +165,27 @@ def test_backward_rejections(lib):
     assert call(dW=FAKE_C + 8) == 3
     assert call(ld_din=10) == 2
     assert call(dIn=None, dW=None) == 0
+
+
+def test_batched_rejections(lib):
+    from paper_2201_03611_amd._lib import RiseGemmProblem, RiseStencilProblem
+
+    plan = ctypes.c_void_p()
+    g = (RiseGemmProblem * 2)()
+    g[0] = RiseGemmProblem(FAKE_C, FAKE_A, FAKE_B, 64, 64, 64, 64, 64, 64, 0, 0)
+    g[1] = RiseGemmProblem(FAKE_C, FAKE_A + 4, FAKE_B, 64, 64, 64, 64, 64, 64, 0, 0)  # unaligned
+    assert lib.rise_plan_create(ctypes.byref(plan), g, 2, None, 0, None, None) == 5
+    g[1] = RiseGemmProblem(FAKE_C, FAKE_A, FAKE_B, 64, 64, 64, 60, 64, 64, 0, 0)  # lda < K
+    assert lib.rise_plan_create(ctypes.byref(plan), g, 2, None, 0, None, None) == 2
+    g[1] = RiseGemmProblem(FAKE_C, FAKE_A, FAKE_B, 64, 64, 60, 64, 64, 64, 1, 0)  # bf16 K % 8
+    assert lib.rise_plan_create(ctypes.byref(plan), g, 2, None, 0, None, None) == 5
+    g[1] = RiseGemmProblem(FAKE_A + 64, FAKE_A, FAKE_B, 64, 64, 64, 64, 64, 64, 0, 0)  # alias
+    assert lib.rise_plan_create(ctypes.byref(plan), g, 2, None, 0, None, None) == 3
+    s = (RiseStencilProblem * 1)()
+    s[0] = RiseStencilProblem(FAKE_C, FAKE_A, FAKE_W, 64, 64, 64, 64, 9, 0)  # k = 9 not batched
+    assert lib.rise_plan_create(ctypes.byref(plan), None, 0, s, 1, None, None) == 5
+    s[0] = RiseStencilProblem(FAKE_C, FAKE_A, FAKE_W, 64, 64, 66, 64, 5, 0)  # ld % 4
+    assert lib.rise_plan_create(ctypes.byref(plan), None, 0, s, 1, None, None) == 5
+    assert lib.rise_plan_create(None, None, 0, None, 0, None, None) == 1
+    assert lib.rise_plan_launch(None, None) == 1
+    assert lib.rise_plan_destroy(None) == 0
