@@ -32,6 +32,37 @@ __device__ __forceinline__ int swz(int r, int c) {
   return r * CH + (c ^ ((r / per) % CH));
 }
 
+// join . join: the wave's TM x TN blocks of 32 x 32 (D layout: lane l holds
+// column l % 32, rows 8*(r/4) + 4*(l/32) + r%4), guarded only on edge tiles.
+template <int TM, int TN>
+__device__ __forceinline__ void store_tile(float* __restrict__ C, int64_t ldc, int M, int N,
+                                           int r0, int c0, int lane, const f32x16 (&acc)[TM][TN]) {
+  const int il = lane & 31, kh = lane >> 5;
+  if (r0 + 32 * TM <= M && c0 + 32 * TN <= N) {
+    float* base = C + (int64_t)(r0 + 4 * kh) * ldc + c0 + il;
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+      for (int j = 0; j < TN; j++)
+#pragma unroll
+        for (int r = 0; r < 16; r++)
+          base[(int64_t)(i * 32 + 8 * (r >> 2) + (r & 3)) * ldc + j * 32] = acc[i][j][r];
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+      const int col = c0 + j * 32 + il;
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = r0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
 template <int MODE>
 struct Parts {
   static constexpr int n = MODE == RISE_MODE_BF16 ? 1 : MODE == RISE_MODE_BF16X3 ? 2 : 3;
@@ -111,55 +142,81 @@ __global__ __launch_bounds__(kThreads, 1) void packed_bf16_kernel(
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
 
+  // Software pipeline of one wave: the fragments of k-step ks+1 are read from
+  // LDS while the matrix cores work on step ks, and on the last step of a slab
+  // the prefetched next slab is written to the other LDS buffer instead.  The
+  // sched_group_barrier hints interleave one LDS instruction after each MFMA so
+  // the LDS traffic hides under the 32-cycle MFMAs.
+  constexpr int KS = BK / 16;                     // k-steps per slab
+  constexpr int NMF = P::nprod * TM * TN;         // MFMAs per k-step
+  constexpr int NRD = NP * (TM + TN);             // fragment reads per k-step
+  constexpr int NWR = NP * (LA + LB);             // LDS writes of one slab
+  const int il = lane & 31, kh = lane >> 5;
+  bf16x8 fa[2][NP][TM], fb[2][NP][TN];
+  auto read_frags = [&](int buf, int ks, int slot) {
+    const int c = 2 * ks + kh;  // this lane's 8 consecutive k within the slab
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+        fa[slot][p][i] = __builtin_bit_cast(bf16x8, As[buf][p][swz<CH>(wm0 + 32 * i + il, c)]);
+#pragma unroll
+      for (int j = 0; j < TN; j++)
+        fb[slot][p][j] = __builtin_bit_cast(bf16x8, Bs[buf][p][swz<CH>(wn0 + 32 * j + il, c)]);
+    }
+  };
+  auto mfmas = [&](int slot) {
+#pragma unroll
+    for (int q = P::nprod - 1; q >= 0; q--)  // small products first
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[slot][P::pa(q)][i],
+                                                              fb[slot][P::pb(q)][j], acc[i][j], 0,
+                                                              0, 0);
+  };
+
   const int nk = Kp / BK;
   if (nk > 0) {
     fetch(0);
     stash(0);
     __syncthreads();
+    read_frags(0, 0, 0);
   }
-  const int il = lane & 31, kh = lane >> 5;
   for (int kt = 0; kt < nk; kt++) {
     const int cur = kt & 1;
-    const bool more = kt + 1 < nk;
-    if (more) fetch((kt + 1) * BK);
+    // Branch-free prefetch keeps the loop body one basic block, so the LDS
+    // writes can interleave with the MFMAs: the last slab fetches itself again
+    // (in bounds) and its copy in the idle buffer is never read.
+    fetch((kt + 1 < nk ? kt + 1 : kt) * BK);
+    __builtin_amdgcn_sched_group_barrier(0x020, NP * (LA + LB), 0);  // global loads first
 #pragma unroll
-    for (int ks = 0; ks < BK / 16; ks++) {
-      const int c = 2 * ks + kh;  // this lane's 8 consecutive k within the slab
-      bf16x8 a[NP][TM], b[NP][TN];
+    for (int ks = 0; ks < KS; ks++) {
+      const int slot = ks & 1;
+      if (ks + 1 < KS) {
+        read_frags(cur, ks + 1, slot ^ 1);
+        mfmas(slot);
 #pragma unroll
-      for (int p = 0; p < NP; p++) {
+        for (int t = 0; t < (NRD < NMF ? NRD : NMF); t++) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+        }
+      } else {
+        stash(cur ^ 1);
+        mfmas(slot);
 #pragma unroll
-        for (int i = 0; i < TM; i++)
-          a[p][i] = __builtin_bit_cast(bf16x8, As[cur][p][swz<CH>(wm0 + 32 * i + il, c)]);
-#pragma unroll
-        for (int j = 0; j < TN; j++)
-          b[p][j] = __builtin_bit_cast(bf16x8, Bs[cur][p][swz<CH>(wn0 + 32 * j + il, c)]);
+        for (int t = 0; t < (NWR < NMF ? NWR : NMF); t++) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+          __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS write
+        }
       }
-#pragma unroll
-      for (int q = P::nprod - 1; q >= 0; q--)  // small products first
-#pragma unroll
-        for (int i = 0; i < TM; i++)
-#pragma unroll
-          for (int j = 0; j < TN; j++)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[P::pa(q)][i], b[P::pb(q)][j],
-                                                                acc[i][j], 0, 0, 0);
     }
-    if (more) stash(cur ^ 1);
     __syncthreads();
+    if (kt + 1 < nk) read_frags(cur ^ 1, 0, 0);
   }
 
-#pragma unroll
-  for (int i = 0; i < TM; i++)
-#pragma unroll
-    for (int j = 0; j < TN; j++) {
-      const int col = n0 + wn0 + j * 32 + il;
-      if (col >= N) continue;
-#pragma unroll
-      for (int r = 0; r < 16; r++) {
-        const int row = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
-      }
-    }
+  store_tile<TM, TN>(C, ldc, M, N, m0 + wm0, n0 + wn0, lane, acc);
 }
 
 // FP8 E4M3 with E8M0 block scales (32 elements along K per scale).
@@ -274,18 +331,7 @@ __global__ __launch_bounds__(kThreads, 1) void packed_fp8_kernel(
     __syncthreads();
   }
 
-#pragma unroll
-  for (int i = 0; i < TM; i++)
-#pragma unroll
-    for (int j = 0; j < TN; j++) {
-      const int col = n0 + wn0 + j * 32 + il;
-      if (col >= N) continue;
-#pragma unroll
-      for (int r = 0; r < 16; r++) {
-        const int row = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
-      }
-    }
+  store_tile<TM, TN>(C, ldc, M, N, m0 + wm0, n0 + wn0, lane, acc);
 }
 
 struct TileRow {
