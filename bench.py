@@ -43,6 +43,11 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    p.add_argument("--only", default=None,
+                   choices=["gemm_f32", "gemm_bf16", "gemm_bf16x3", "gemm_fp8", "stencil",
+                            "conv_fwd", "conv_bwd", "batched"],
+                   help="run one kernel of the path --reps times (for profilers) and exit")
+    p.add_argument("--reps", type=int, default=5)
     return p.parse_args()
 
 
@@ -84,6 +89,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+
+    if args.only:
+        run_only(args.only, args.reps, rise, ri, torch, dev, stream)
+        return
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, device=dev, dtype=torch.float32)  # 1 GiB
@@ -177,6 +186,95 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(ri, np, A, B, img, wts, value, ms_step)
     print(json.dumps(result), flush=True)
+
+
+def run_only(what, reps, rise, ri, torch, dev, stream):
+    """One kernel of the path, `reps` launches, on seeded synthetic data of the
+    benchmark sizes (for rocprofv3 runs)."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(1000)
+    if what.startswith("gemm"):
+        n = 4096 if what == "gemm_f32" else 8192
+        mode = what[5:]
+        A = torch.randn((n, n), device=dev, generator=g)
+        B = torch.randn((n, n), device=dev, generator=g)
+        C = torch.empty((n, n), device=dev)
+        ws = torch.empty(max(rise.rise_gemm_workspace(n, n, n, mode), 1), device=dev,
+                         dtype=torch.uint8)
+        call = lambda i: rise.rise_gemm(C, A, B, n, n, n, lda=n, ldb=n, ldc=n, mode=mode, ws=ws,
+                                        stream=stream)
+    elif what == "stencil":
+        imgs = [torch.rand((H, W), device=dev, generator=g) for _ in range(6)]
+        outs = [torch.empty((H, W), device=dev) for _ in range(6)]
+        w = torch.from_numpy(ri.gaussian_weights(KS, 1.0)).to(dev)
+        call = lambda i: rise.rise_stencil2d(outs[i % 6], imgs[i % 6], w, H, W, ld_out=W,
+                                             ld_in=W, kh=KS, kw=KS, stream=stream)
+    elif what.startswith("conv"):
+        Bn, C, Hc, Wc = 32, 64, 512, 512
+        x = torch.randn((Bn, Hc, Wc, C), device=dev, generator=g).to(torch.bfloat16)
+        dout = torch.randn((Bn, Hc, Wc, C), device=dev, generator=g).to(torch.bfloat16)
+        w = torch.randn((C, C, 3, 3), device=dev, generator=g) * 0.02
+        if what == "conv_fwd":
+            out = torch.empty_like(x)
+            ws = torch.empty(rise.rise_conv2d_workspace(C, C), device=dev, dtype=torch.uint8)
+            call = lambda i: rise.rise_conv2d(out, x, w, Bn, C, C, Hc, Wc, ws=ws, stream=stream)
+        else:
+            dIn = torch.empty_like(x)
+            dW = torch.empty_like(w)
+            ws = torch.empty(rise.rise_conv2d_backward_workspace(Bn, C, C, Hc, Wc), device=dev,
+                             dtype=torch.uint8)
+            call = lambda i: rise.rise_conv2d_backward(dIn, dW, dout, x, w, Bn, C, C, Hc, Wc,
+                                                       ws=ws, stream=stream)
+    else:  # batched
+        plan, keep = batched_plan(rise, ri, torch, dev, "f32")
+        call = lambda i: plan.launch(stream)
+    for i in range(reps):
+        call(i)
+    torch.cuda.synchronize()
+    print(json.dumps({"only": what, "reps": reps}), flush=True)
+
+
+def batched_plan(rise, ri, torch, dev, dtype):
+    """The batched workload: 512 GEMMs with M, N, K uniform on {64, 96, ..., 1024}
+    (FP32 or bf16 operands) and 256 FP32 stencils, side U{256..2048}, k in {3, 5, 7},
+    weights summing to 1, clamp padding; device data from a seeded generator."""
+    import numpy as np
+
+    from paper_2201_03611_amd._lib import RISE_BF16, RISE_F32
+
+    sizes = ri.batched_gemm_sizes()
+    specs = ri.batched_stencil_specs()
+    g = torch.Generator(device=dev)
+    g.manual_seed(ri.SEED_BATCHED)
+    keep = []
+    gp = (rise.RiseGemmProblem * 512)()
+    flops = 0.0
+    for i in range(512):
+        M, N, K = (int(v) for v in sizes[i])
+        A = torch.rand((M, K), device=dev, generator=g) * 2 - 1
+        B = torch.rand((K, N), device=dev, generator=g) * 2 - 1
+        if dtype == "bf16":
+            A, B = A.to(torch.bfloat16), B.to(torch.bfloat16)
+        C = torch.empty((M, N), device=dev)
+        keep += [A, B, C]
+        gp[i] = rise.RiseGemmProblem(C.data_ptr(), A.data_ptr(), B.data_ptr(), M, N, K, K, N, N,
+                                     RISE_BF16 if dtype == "bf16" else RISE_F32, 0)
+        flops += 2.0 * M * N * K
+    sp = (rise.RiseStencilProblem * 256)()
+    rng = ri.rng(ri.SEED_BATCHED + 200)
+    bytes_ = 0.0
+    for i in range(256):
+        side, k = (int(v) for v in specs[i])
+        img = torch.rand((side, side), device=dev, generator=g)
+        w = torch.from_numpy(ri.random_weights(rng, k)).to(dev)
+        out = torch.empty_like(img)
+        keep += [img, w, out]
+        sp[i] = rise.RiseStencilProblem(out.data_ptr(), img.data_ptr(), w.data_ptr(), side, side,
+                                        side, side, k, 0)
+        bytes_ += 8.0 * side * side
+    plan = rise.Plan(gp, 512, sp, 256)
+    keep.append((flops, bytes_, gp, sp))
+    return plan, keep
 
 
 def precision_leg(rise, ri, np, torch, dev, stream):

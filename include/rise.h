@@ -253,7 +253,8 @@ typedef struct {
 } rise_gemm_problem;
 
 /* One stencil of a batch: as rise_stencil2d with a square window of side k in
- * {1, 3, 5, 7}; images 16-byte aligned with ld_in, ld_out multiples of 4. */
+ * {1, 3, 5, 7} (16-byte vector loads when both images are 16-byte aligned with
+ * ld_in, ld_out multiples of 4, scalar loads otherwise). */
 typedef struct {
   float* out;
   const float* in;

@@ -499,11 +499,11 @@ rise_status rise_autotune_batched(const char* table_path, void* stream) {
   };
   for (int k = 0; k < num_kinds() && st == RISE_OK; k++) {
     if (kind_is_stencil(k)) {
-      const int side = 1 + 2 * (k - (num_kinds() - 4));
+      const int side = kind_stencil_side(k);
       rise_stencil_problem sp{(float*)C, (const float*)A, (const float*)w, n, n, n, n, side,
                               RISE_PAD_CLAMP};
       double t = 0;
-      st = measure(nullptr, &sp, -1, &t);
+      st = measure(nullptr, &sp, k, &t);
       fprintf(f, "%s %.6f %.8f\n", kind_name(k), t, 0.0);
     } else {
       double t1 = 0, t2 = 0;

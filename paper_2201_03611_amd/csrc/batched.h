@@ -19,6 +19,7 @@ int plan_kind(const PlanImpl* p, int i);
 const char* kind_name(int k);
 int num_kinds();
 int kind_is_stencil(int k);
+int kind_stencil_side(int k);
 int kind_dtype(int k);
 int kind_opb(int k);
 

@@ -30,7 +30,8 @@ enum Kind : int {
   F32_64x64_N, F32_64x64_T, F32_128x64_N, F32_128x64_T, F32_64x128_N, F32_64x128_T,
   F32_128x128_N, F32_128x128_T,
   BF16_64x64_N, BF16_64x64_T, BF16_128x128_N, BF16_128x128_T,
-  STENCIL_1, STENCIL_3, STENCIL_5, STENCIL_7,
+  STENCIL_1, STENCIL_3, STENCIL_5, STENCIL_7,                   // 16-byte vector paths
+  STENCIL_1S, STENCIL_3S, STENCIL_5S, STENCIL_7S,               // any alignment / ld
   NUM_KINDS
 };
 struct KindShape {
@@ -39,6 +40,7 @@ struct KindShape {
 const KindShape kShape[NUM_KINDS] = {
     {64, 64, 32}, {64, 64, 32}, {128, 64, 32}, {128, 64, 32}, {64, 128, 32}, {64, 128, 32},
     {128, 128, 32}, {128, 128, 32}, {64, 64, 32}, {64, 64, 32}, {128, 128, 32}, {128, 128, 32},
+    {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0},
     {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}};
 constexpr int kStencilRows = 16;
 
@@ -80,10 +82,10 @@ __device__ __forceinline__ void run_item(const Desc& d, int tile, char* lds) {
 #define RISE_BF16(BM, BN, TB)                                                                   \
   tiles::gemm_bf16_tile<BM, BN, 32, TB>(d.out, d.ldc, ha, d.lda, hb, d.ldb, d.M, d.N, d.K,      \
                                         tm * BM, tn * BN, cl)
-#define RISE_STENCIL(K)                                                                         \
-  tiles::stencil_lds_tile<K, true, kStencilRows>(d.out, d.ldc, fa, d.lda, d.M, d.N, fb,         \
-                                                 d.zero_pad, tm * kStencilRows,                \
-                                                 tn * tiles::kStencilTX, sl)
+#define RISE_STENCIL(K, VEC)                                                                    \
+  tiles::stencil_lds_tile<K, VEC, kStencilRows>(d.out, d.ldc, fa, d.lda, d.M, d.N, fb,          \
+                                                d.zero_pad, tm * kStencilRows,                 \
+                                                tn * tiles::kStencilTX, sl)
   switch (d.kind) {
     case F32_64x64_N: RISE_F32(64, 64, false); break;
     case F32_64x64_T: RISE_F32(64, 64, true); break;
@@ -97,10 +99,14 @@ __device__ __forceinline__ void run_item(const Desc& d, int tile, char* lds) {
     case BF16_64x64_T: RISE_BF16(64, 64, true); break;
     case BF16_128x128_N: RISE_BF16(128, 128, false); break;
     case BF16_128x128_T: RISE_BF16(128, 128, true); break;
-    case STENCIL_1: RISE_STENCIL(1); break;
-    case STENCIL_3: RISE_STENCIL(3); break;
-    case STENCIL_5: RISE_STENCIL(5); break;
-    case STENCIL_7: RISE_STENCIL(7); break;
+    case STENCIL_1: RISE_STENCIL(1, true); break;
+    case STENCIL_3: RISE_STENCIL(3, true); break;
+    case STENCIL_5: RISE_STENCIL(5, true); break;
+    case STENCIL_7: RISE_STENCIL(7, true); break;
+    case STENCIL_1S: RISE_STENCIL(1, false); break;
+    case STENCIL_3S: RISE_STENCIL(3, false); break;
+    case STENCIL_5S: RISE_STENCIL(5, false); break;
+    case STENCIL_7S: RISE_STENCIL(7, false); break;
     default: break;
   }
 #undef RISE_F32
@@ -144,12 +150,14 @@ struct Cost {
 Cost g_default_cost[NUM_KINDS] = {
     {1.0, 0.0040}, {1.0, 0.0042}, {1.2, 0.0068}, {1.2, 0.0070}, {1.2, 0.0068}, {1.2, 0.0070},
     {1.5, 0.0125}, {1.5, 0.0128}, {1.0, 0.0014}, {1.0, 0.0016}, {1.5, 0.0040}, {1.5, 0.0044},
-    {1.0, 0.0},    {1.5, 0.0},    {2.0, 0.0},    {2.5, 0.0}};
+    {1.0, 0.0},    {1.5, 0.0},    {2.0, 0.0},    {2.5, 0.0},
+    {1.5, 0.0},    {2.0, 0.0},    {2.5, 0.0},    {3.0, 0.0}};
 
 const char* kKindNames[NUM_KINDS] = {
     "f32_64x64_N", "f32_64x64_T", "f32_128x64_N", "f32_128x64_T", "f32_64x128_N",
     "f32_64x128_T", "f32_128x128_N", "f32_128x128_T", "bf16_64x64_N", "bf16_64x64_T",
-    "bf16_128x128_N", "bf16_128x128_T", "stencil_1", "stencil_3", "stencil_5", "stencil_7"};
+    "bf16_128x128_N", "bf16_128x128_T", "stencil_1", "stencil_3", "stencil_5", "stencil_7",
+    "stencil_1_scalar", "stencil_3_scalar", "stencil_5_scalar", "stencil_7_scalar"};
 
 bool load_costs(const char* path, Cost* cost) {
   for (int k = 0; k < NUM_KINDS; k++) cost[k] = g_default_cost[k];
@@ -232,8 +240,6 @@ rise_status check_stencil_problem(const rise_stencil_problem& p, int i) {
   if (p.H == 0 || p.W == 0) return RISE_OK;
   if (!p.out || !p.in || !p.w) return fail(RISE_ERR_NULL, where("NULL pointer"));
   if (p.ld_in < p.W || p.ld_out < p.W) return fail(RISE_ERR_SHAPE, where("ld"));
-  if (!aligned16(p.in) || !aligned16(p.out) || p.ld_in % 4 || p.ld_out % 4)
-    return fail(RISE_ERR_UNSUPPORTED, where("images must be 16-byte aligned, ld multiples of 4"));
   uintptr_t olo = (uintptr_t)p.out, ohi = olo + (uintptr_t)(((p.H - 1) * p.ld_out + p.W) * 4);
   uintptr_t ilo = (uintptr_t)p.in, ihi = ilo + (uintptr_t)(((p.H - 1) * p.ld_in + p.W) * 4);
   uintptr_t wlo = (uintptr_t)p.w, whi = wlo + (uintptr_t)(p.k * p.k * 4);
@@ -290,7 +296,9 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
   }
   for (int i = 0; i < ns; i++) {
     const rise_stencil_problem& p = st[i];
-    const int kind = STENCIL_1 + (p.k - 1) / 2;
+    const bool vec = aligned16(p.in) && aligned16(p.out) && p.ld_in % 4 == 0 && p.ld_out % 4 == 0;
+    const int kind = forced_kind >= STENCIL_1 ? forced_kind
+                                              : (vec ? STENCIL_1 : STENCIL_1S) + (p.k - 1) / 2;
     plan->kinds.push_back(kind);
     Desc d{p.out, p.in, p.w, p.ld_in, 0, p.ld_out, (int)p.H, (int)p.W, p.k, kind,
            ceil_div(p.W, tiles::kStencilTX), p.pad == RISE_PAD_ZERO, 0};
@@ -386,6 +394,7 @@ int plan_kind(const PlanImpl* p, int i) { return i >= 0 && i < (int)p->kinds.siz
 const char* kind_name(int k) { return k >= 0 && k < NUM_KINDS ? kKindNames[k] : ""; }
 int num_kinds() { return NUM_KINDS; }
 int kind_is_stencil(int k) { return k >= STENCIL_1; }
+int kind_stencil_side(int k) { return 1 + 2 * ((k - STENCIL_1) % 4); }
 int kind_dtype(int k) { return k >= BF16_64x64_N && k <= BF16_128x128_T ? RISE_BF16 : RISE_F32; }
 int kind_opb(int k) { return k < STENCIL_1 ? (k & 1) : -1; }
 

@@ -184,8 +184,8 @@ def test_batched_rejections(lib):
     s = (RiseStencilProblem * 1)()
     s[0] = RiseStencilProblem(FAKE_C, FAKE_A, FAKE_W, 64, 64, 64, 64, 9, 0)  # k = 9 not batched
     assert lib.rise_plan_create(ctypes.byref(plan), None, 0, s, 1, None, None) == 5
-    s[0] = RiseStencilProblem(FAKE_C, FAKE_A, FAKE_W, 64, 64, 66, 64, 5, 0)  # ld % 4
-    assert lib.rise_plan_create(ctypes.byref(plan), None, 0, s, 1, None, None) == 5
+    s[0] = RiseStencilProblem(FAKE_C, FAKE_A, FAKE_W, 64, 64, 63, 64, 5, 0)  # ld < W
+    assert lib.rise_plan_create(ctypes.byref(plan), None, 0, s, 1, None, None) == 2
     assert lib.rise_plan_create(None, None, 0, None, 0, None, None) == 1
     assert lib.rise_plan_launch(None, None) == 1
     assert lib.rise_plan_destroy(None) == 0

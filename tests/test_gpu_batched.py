@@ -198,7 +198,7 @@ def test_autotune_table(rise):
     rise.rise_autotune_batched(path)
     rows = [l.split() for l in open(path) if l.strip()]
     names = {r[0] for r in rows}
-    assert len(rows) == 16 and "f32_128x128_N" in names and "stencil_5" in names
+    assert len(rows) == 20 and "f32_128x128_N" in names and "stencil_5_scalar" in names
     for r in rows:
         a, b = float(r[1]), float(r[2])
         assert a + b * 1024 > 0
