@@ -60,17 +60,21 @@ __global__ void conv_prep_weights(uint16_t* __restrict__ dst, const float* __res
   }
 }
 
-// 16-byte chunk c of halo pixel p (CH chunks per pixel) -> LDS chunk index
+// 16-byte chunk c of halo pixel p (CH chunks per pixel) -> LDS chunk index.  A
+// 16-lane group of ds_read_b128 is served from one 256-byte line (64 banks): the
+// XOR key changes every 16/CH pixels so 16 consecutive pixels at one logical
+// chunk use 16 distinct slots.
 template <int CH>
 __device__ __forceinline__ int halo_slot(int p, int c) {
-  return p * CH + (c ^ (p & (CH - 1) & 7));
+  return p * CH + (c ^ ((p / (16 / CH)) % CH));
 }
 // chunk k of weight row o -> LDS chunk index; rows are padded to KCP chunks (a
-// multiple of 8) so the XOR with the row's low bits stays inside the row
+// multiple of 8, KCP = 8 mod 16 for the shapes here) so the XOR stays inside the
+// row, and the key (o / 2) spreads 16 consecutive rows over 16 slots
 template <int KCP>
 __device__ __forceinline__ int wslot(int o, int k) {
   static_assert(KCP % 8 == 0, "padded row");
-  return o * KCP + (k ^ (o & 7));
+  return o * KCP + (k ^ ((o >> 1) & 7));
 }
 
 template <int CI, int CO>

@@ -25,10 +25,13 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// row r, 16-byte chunk c of a slab with CH chunks per row -> chunk index in LDS
+// row r, 16-byte chunk c of a slab with CH chunks per row -> chunk index in LDS.
+// gfx950's LDS serves a 16-lane group of ds_read_b128 from one 256-byte line of
+// 64 banks; the XOR key changes every 16/CH rows so that 16 consecutive rows
+// read at the same logical chunk land in 16 distinct 16-byte slots.
 template <int CH>
 __device__ __forceinline__ int swz(int r, int c) {
-  constexpr int per = 8 / CH;  // rows sharing one 128-byte bank line
+  constexpr int per = 16 / CH;  // rows sharing one 256-byte bank line
   return r * CH + (c ^ ((r / per) % CH));
 }
 

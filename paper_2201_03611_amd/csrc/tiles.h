@@ -206,9 +206,12 @@ struct Bf16Cfg {
   static constexpr int LDS_CHUNKS = 2 * (BM + BN) * CH;
 };
 
+// row r, 16-byte chunk c -> LDS chunk index; the XOR key changes every 16/CH rows
+// so 16 consecutive rows at one logical chunk hit distinct slots of a 256-byte
+// (64-bank) line
 template <int CH>
 __device__ __forceinline__ int swz16(int r, int c) {
-  constexpr int per = 8 / CH;  // rows sharing one 128-byte bank line
+  constexpr int per = 16 / CH;  // rows sharing one 256-byte bank line
   return r * CH + (c ^ ((r / per) % CH));
 }
 
