@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-precision", action="store_true", help="skip the 8192^3 precision leg")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the batched and stencil-layer legs")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     p.add_argument("--only", default=None,
@@ -183,6 +185,9 @@ def main():
 
     if not args.no_precision:
         result["precision"] = precision_leg(rise, ri, np, torch, dev, stream)
+    if not args.no_extra:
+        result["batched"] = batched_leg(rise, ri, torch, dev, stream)
+        result["layer"] = layer_leg(rise, torch, dev, stream)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(ri, np, A, B, img, wts, value, ms_step)
     print(json.dumps(result), flush=True)
@@ -275,6 +280,103 @@ def batched_plan(rise, ri, torch, dev, dtype):
     plan = rise.Plan(gp, 512, sp, 256)
     keep.append((flops, bytes_, gp, sp))
     return plan, keep
+
+
+def event_ms(torch, stream, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched_leg(rise, ri, torch, dev, stream):
+    """512 GEMMs + 256 stencils: one graph launch of the persistent kernel, the same
+    kernel without the graph, and 768 separate one-problem launches; lower bounds
+    from the spec peaks (additive: compute + memory; overlapped: their max)."""
+    out = {}
+    for dtype in ("f32", "bf16"):
+        plan, keep = batched_plan(rise, ri, torch, dev, dtype)
+        flops, sbytes, gp, sp = keep[-1]
+        gbytes = 0.0
+        for i in range(512):
+            p = gp[i]
+            e = 4 if dtype == "f32" else 2
+            gbytes += e * (p.M * p.K + p.K * p.N) + 4 * p.M * p.N
+        ms_graph = event_ms(torch, stream, lambda: plan.launch(stream), 10)
+        ms_direct = event_ms(torch, stream, lambda: plan.launch_direct(stream), 10)
+
+        def separate():
+            for i in range(512):
+                A, B, C = keep[3 * i:3 * i + 3]
+                q = gp[i]
+                rise.rise_gemm(C, A, B, q.M, q.N, q.K, lda=q.lda, ldb=q.ldb, ldc=q.ldc,
+                               stream=stream)
+            for i in range(256):
+                img, w, o = keep[1536 + 3 * i:1536 + 3 * i + 3]
+                q = sp[i]
+                rise.rise_stencil2d(o, img, w, q.H, q.W, ld_out=q.ld_out, ld_in=q.ld_in,
+                                    kh=q.k, kw=q.k, pad=q.pad, stream=stream)
+
+        ms_sep = event_ms(torch, stream, separate, 3) if dtype == "f32" else None
+        peak = PEAK_FP32_MFMA if dtype == "f32" else PEAK_BF16
+        t_flop = flops / (peak * 1e12) * 1e3
+        t_mem = (sbytes + gbytes) / (PEAK_HBM * 1e9) * 1e3
+        out[dtype] = {"ms_graph": round(ms_graph, 3), "ms_direct": round(ms_direct, 3),
+                      "ms_separate_launches": round(ms_sep, 3) if ms_sep else None,
+                      "items": plan.items(), "gemm_gflop": round(flops / 1e9, 1),
+                      "stencil_gb": round(sbytes / 1e9, 2),
+                      "bound_ms_additive": round(t_flop + t_mem, 3),
+                      "bound_ms_overlapped": round(max(t_flop, t_mem), 3),
+                      "frac_of_additive_bound": round((t_flop + t_mem) / ms_graph, 3),
+                      "frac_of_overlapped_bound": round(max(t_flop, t_mem) / ms_graph, 3)}
+        if ms_sep:
+            out[dtype]["speedup_vs_separate"] = round(ms_sep / ms_graph, 2)
+        plan.destroy()
+        del keep
+        torch.cuda.empty_cache()
+    out["note"] = ("separate launches: 512 rise_gemm + 256 rise_stencil2d calls with the "
+                   "library's default tiles (FP32 set only; the bf16 set needs its operand "
+                   "preparation per call)")
+    return out
+
+
+def layer_leg(rise, torch, dev, stream):
+    """Stencil layer, batch 32, 64 -> 64 channels, 512 x 512, 3 x 3, bf16 NHWC:
+    forward, dIn and dW (each 618.5 GFLOP), seeded device data."""
+    Bn, C, Hc, Wc = 32, 64, 512, 512
+    g = torch.Generator(device=dev)
+    g.manual_seed(1006)
+    x = torch.randn((Bn, Hc, Wc, C), device=dev, generator=g).to(torch.bfloat16)
+    dout = torch.randn((Bn, Hc, Wc, C), device=dev, generator=g).to(torch.bfloat16)
+    w = torch.randn((C, C, 3, 3), device=dev, generator=g) * 0.02
+    out = torch.empty_like(x)
+    dIn = torch.empty_like(x)
+    dW = torch.empty_like(w)
+    wsf = torch.empty(rise.rise_conv2d_workspace(C, C), device=dev, dtype=torch.uint8)
+    wsb = torch.empty(rise.rise_conv2d_backward_workspace(Bn, C, C, Hc, Wc), device=dev,
+                      dtype=torch.uint8)
+    fl = 2.0 * Bn * Hc * Wc * C * C * 9
+    act = 2.0 * Bn * Hc * Wc * C
+    ms_f = event_ms(torch, stream, lambda: rise.rise_conv2d(out, x, w, Bn, C, C, Hc, Wc, ws=wsf,
+                                                            stream=stream), 10)
+    ms_di = event_ms(torch, stream, lambda: rise.rise_conv2d_backward(
+        dIn, None, dout, x, w, Bn, C, C, Hc, Wc, ws=wsb, stream=stream), 10)
+    ms_dw = event_ms(torch, stream, lambda: rise.rise_conv2d_backward(
+        None, dW, dout, x, w, Bn, C, C, Hc, Wc, ws=wsb, stream=stream), 10)
+    res = {}
+    for name, ms, by in (("forward", ms_f, 2 * act), ("dIn", ms_di, 2 * act), ("dW", ms_dw, 2 * act)):
+        tf = fl / (ms * 1e-3) / 1e12
+        gbs = by / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 3), "tflops": round(tf, 1),
+                     "frac_bf16_peak": round(tf / PEAK_BF16, 3), "gbps": round(gbs, 1),
+                     "frac_hbm_peak": round(gbs / PEAK_HBM, 3)}
+    res["bound_ms_forward"] = round(max(fl / (PEAK_BF16 * 1e9), 2 * act / (PEAK_HBM * 1e6)), 3)
+    return res
 
 
 def precision_leg(rise, ri, np, torch, dev, stream):
