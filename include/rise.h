@@ -156,9 +156,18 @@ rise_status rise_prep_operand(void* out, int64_t rows_out, int64_t k_out, const 
  *    4 adjacent outputs per row from it;
  *  RISE_STENCIL_STREAM: each wavefront walks down a 256-column strip segment of
  *    `rows` output rows, keeps the window rows in registers and receives its
- *    neighbours' columns through wavefront shifts.
+ *    neighbours' columns through wavefront shifts;
+ *  RISE_STENCIL_LDS_PIPE: the LDS halo tile of RISE_STENCIL_LDS_TILE, run by a
+ *    resident grid (a few workgroups per compute unit) in which each workgroup
+ *    walks a fixed list of tiles and fetches tile i+1 into registers while it
+ *    reduces tile i from a double-buffered LDS tile, so HBM traffic and the
+ *    k*k FMAs overlap inside every workgroup.
  * rise_stencil_schedules() lists the supported (variant, rows) pairs. */
-typedef enum { RISE_STENCIL_LDS_TILE = 0, RISE_STENCIL_STREAM = 1 } rise_stencil_variant;
+typedef enum {
+  RISE_STENCIL_LDS_TILE = 0,
+  RISE_STENCIL_STREAM = 1,
+  RISE_STENCIL_LDS_PIPE = 2
+} rise_stencil_variant;
 typedef struct {
   int32_t variant; /* rise_stencil_variant */
   int32_t rows;

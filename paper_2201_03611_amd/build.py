@@ -50,6 +50,9 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+    # resolve every symbol now, so a missing kernel instantiation fails the build
+    import ctypes
+    ctypes.CDLL(OUT + ".tmp", mode=os.RTLD_NOW)
     os.replace(OUT + ".tmp", OUT)
     return OUT
 

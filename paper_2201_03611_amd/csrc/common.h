@@ -16,6 +16,8 @@ namespace rise {
 rise_status fail(rise_status s, const std::string& msg);
 void clear_error();
 rise_status check_launch(const char* what);
+// compute units of the current device (cached per device)
+int device_cu_count();
 
 // ---------------------------------------------------------------------------
 // vector types of the gfx950 matrix-core builtins

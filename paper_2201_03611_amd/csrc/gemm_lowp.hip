@@ -81,18 +81,23 @@ struct Parts {
   }
 };
 
-template <int BM, int BN, int BK, int MODE>
-__global__ __launch_bounds__(kThreads, 1) void packed_bf16_kernel(
+// NW waves per workgroup in an (NW/2) x 2 grid: with 8 waves two waves share
+// each SIMD, so one wave's barrier and LDS waits are covered by the other's
+// MFMAs (at 0.75 fragment reads per MFMA instead of 0.5, which the LDS
+// bandwidth available to 8 waves sustains).
+template <int BM, int BN, int BK, int MODE, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void packed_bf16_kernel(
     float* __restrict__ C, int64_t ldc, const uint16_t* __restrict__ Ap,
     const uint16_t* __restrict__ Bp, int M, int N, int Kp, int Mp, int Np, int tiles_m,
     int tiles_n) {
   using P = Parts<MODE>;
   constexpr int NP = P::n;
   constexpr int CH = BK / 8;                 // 16-byte chunks per slab row
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int T = 64 * NW;                 // threads
+  constexpr int WM = BM / (NW / 2), WN = BN / 2;
   constexpr int TM = WM / 32, TN = WN / 32;
-  constexpr int LA = BM * BK / 8 / kThreads;  // chunks per thread per part
-  constexpr int LB = BN * BK / 8 / kThreads;
+  constexpr int LA = BM * BK / 8 / T;        // chunks per thread per part
+  constexpr int LB = BN * BK / 8 / T;
   static_assert(LA >= 1 && LB >= 1, "tile too small");
 
   __shared__ i32x4 As[2][NP][BM * CH];
@@ -110,18 +115,19 @@ __global__ __launch_bounds__(kThreads, 1) void packed_bf16_kernel(
   // requested one slab earlier, is written to LDS, so every global load has
   // about two slabs of MFMA time to arrive; the 256 x 256 tiles keep one set.
   constexpr int NSET = BM >= 256 ? 1 : 2;
+  static_assert(NW == 4 || NW == 8, "wave grid");
   i32x4 ra[NSET][NP][LA], rb[NSET][NP][LB];
   auto fetch = [&](int set, int k0) {
 #pragma unroll
     for (int p = 0; p < NP; p++) {
 #pragma unroll
       for (int q = 0; q < LA; q++) {
-        int c = tid + kThreads * q, r = c / CH, ch = c % CH;
+        int c = tid + T * q, r = c / CH, ch = c % CH;
         ra[set][p][q] = *reinterpret_cast<const i32x4*>(Ap + p * planeA + (int64_t)(m0 + r) * Kp + k0 + ch * 8);
       }
 #pragma unroll
       for (int q = 0; q < LB; q++) {
-        int c = tid + kThreads * q, r = c / CH, ch = c % CH;
+        int c = tid + T * q, r = c / CH, ch = c % CH;
         rb[set][p][q] = *reinterpret_cast<const i32x4*>(Bp + p * planeB + (int64_t)(n0 + r) * Kp + k0 + ch * 8);
       }
     }
@@ -131,12 +137,12 @@ __global__ __launch_bounds__(kThreads, 1) void packed_bf16_kernel(
     for (int p = 0; p < NP; p++) {
 #pragma unroll
       for (int q = 0; q < LA; q++) {
-        int c = tid + kThreads * q;
+        int c = tid + T * q;
         As[buf][p][swz<CH>(c / CH, c % CH)] = ra[set][p][q];
       }
 #pragma unroll
       for (int q = 0; q < LB; q++) {
-        int c = tid + kThreads * q;
+        int c = tid + T * q;
         Bs[buf][p][swz<CH>(c / CH, c % CH)] = rb[set][p][q];
       }
     }
@@ -351,12 +357,189 @@ __global__ __launch_bounds__(kThreads, 1) void packed_fp8_kernel(
   store_tile<TM, TN>(C, ldc, M, N, m0 + wm0, n0 + wn0, lane, acc);
 }
 
+// ---------------------------------------------------------------------------
+// BF16 / split-BF16 kernel with asynchronous slab copies: the same tiling and
+// contraction as packed_bf16_kernel, but each slab goes from global memory
+// straight into LDS (gfx950 global_load_lds_dwordx4: lane i's 16 bytes land
+// at base + 16 i) through a ring of STAGES buffers.  The copy of slab kt +
+// STAGES - 1 is issued right after the barrier that opens slab kt, so each
+// copy has STAGES - 1 slabs of matrix-core time to arrive, and no registers
+// hold data in transit.  Copy completion is tracked only by vmcnt, so the
+// waits are explicit: before the barrier of slab kt a wave waits until at
+// most the copies of the STAGES - 2 newer slabs are outstanding, and the
+// barrier then publishes every wave's part of slab kt.  The barrier is a
+// bare s_barrier (a workgroup fence would wait for all copies in flight).
+// The swizzle is applied on the global side: lane i of a copy fetches the
+// logical chunk that belongs in LDS slot base + i.
+// (the instruction text exists only in the device pass)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt field is 6 bits");
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+#endif
+}
+__device__ __forceinline__ void wait_lgkmcnt0() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#endif
+}
+__device__ __forceinline__ void raw_barrier() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_barrier" ::: "memory");
+#endif
+}
+// 16 bytes per lane, global -> LDS at lds_base + 16 * lane (lds_base wave-uniform)
+__device__ __forceinline__ void copy16_to_lds(const void* src, void* lds_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
+#endif
+}
+
+template <int BM, int BN, int BK, int STAGES, int MODE, bool XPF>
+__global__ __launch_bounds__(kThreads, 1) void packed_bf16_async_kernel(
+    float* __restrict__ C, int64_t ldc, const uint16_t* __restrict__ Ap,
+    const uint16_t* __restrict__ Bp, int M, int N, int Kp, int Mp, int Np, int tiles_m,
+    int tiles_n) {
+  using P = Parts<MODE>;
+  constexpr int NP = P::n;
+  constexpr int CH = BK / 8;              // 16-byte chunks per slab row
+  constexpr int SLOTS = (BM + BN) * CH;   // chunks per part per stage: A rows, then B rows
+  constexpr int NCP = SLOTS / kThreads;   // copies per thread per part per slab
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 32, TN = WN / 32;
+  constexpr int KS = BK / 16;
+  static_assert(SLOTS % kThreads == 0 && STAGES >= 3, "slab shape");
+  static_assert(BM % 16 == 0, "the B rows start on a whole swizzle period");
+  constexpr int INFLIGHT = (STAGES - 2) * NP * NCP;  // copies allowed outstanding at a barrier
+
+  __shared__ i32x4 lds[STAGES][NP][SLOTS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+  int tm, tn;
+  grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, 4, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int64_t planeA = (int64_t)Mp * Kp, planeB = (int64_t)Np * Kp;
+
+  // copy q of this lane fills slot (wave * NCP + q) * 64 + lane of every part
+  const uint16_t* src[NCP];
+  int64_t plane[NCP];
+#pragma unroll
+  for (int q = 0; q < NCP; q++) {
+    const int slot = (wave * NCP + q) * 64 + lane;
+    const int r = slot / CH, pc = slot % CH;
+    const int c = pc ^ ((r / (16 / CH)) % CH);  // inverse of swz<CH> (an involution per row)
+    if (r < BM) {
+      src[q] = Ap + (int64_t)(m0 + r) * Kp + c * 8;
+      plane[q] = planeA;
+    } else {
+      src[q] = Bp + (int64_t)(n0 + r - BM) * Kp + c * 8;
+      plane[q] = planeB;
+    }
+  }
+  const int nk = Kp / BK;
+  auto issue = [&](int kt, int buf) {  // slab min(kt, nk - 1) -> ring buffer buf
+    const int k0 = (kt < nk ? kt : nk - 1) * BK;
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+#pragma unroll
+      for (int q = 0; q < NCP; q++)
+        copy16_to_lds(src[q] + p * plane[q] + k0, &lds[buf][p][(wave * NCP + q) * 64]);
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  const int il = lane & 31, kh = lane >> 5;
+  bf16x8 fa[2][NP][TM], fb[2][NP][TN];
+  auto read_frags = [&](int buf, int ks, int slot) {
+    const int c = 2 * ks + kh;
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+        fa[slot][p][i] = __builtin_bit_cast(bf16x8, lds[buf][p][swz<CH>(wm0 + 32 * i + il, c)]);
+#pragma unroll
+      for (int j = 0; j < TN; j++)
+        fb[slot][p][j] = __builtin_bit_cast(bf16x8, lds[buf][p][swz<CH>(BM + wn0 + 32 * j + il, c)]);
+    }
+  };
+  auto mfmas = [&](int slot) {
+#pragma unroll
+    for (int q = P::nprod - 1; q >= 0; q--)  // small products first
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[slot][P::pa(q)][i],
+                                                              fb[slot][P::pb(q)][j], acc[i][j], 0,
+                                                              0, 0);
+  };
+  constexpr int NMF = P::nprod * TM * TN;
+  constexpr int NRD = NP * (TM + TN);
+
+  // XPF: the barrier that opens slab kt also publishes slab kt + 1, so the
+  // first fragments of slab kt + 1 are read under the last MFMAs of slab kt
+  // (no LDS-latency bubble after the barrier), at the price of one slab less
+  // lead time for the copies.
+  constexpr int WAIT = XPF ? (STAGES - 3) * NP * NCP : INFLIGHT;
+  static_assert(!XPF || STAGES >= 4, "cross-slab prefetch needs four buffers");
+  static_assert(!XPF || KS % 2 == 0, "fragment slots alternate per k-step: even k-steps per slab");
+  if (nk > 0) {
+#pragma unroll
+    for (int st = 0; st < STAGES - 1; st++) issue(st, st);
+    if (XPF) {
+      wait_vmcnt<INFLIGHT>();
+      raw_barrier();
+      read_frags(0, 0, 0);
+    }
+  }
+  for (int kt = 0; kt < nk; kt++) {
+    const int buf = kt % STAGES;
+    wait_vmcnt<WAIT>();  // this wave's copies of slab kt (XPF: kt + 1) have landed
+    wait_lgkmcnt0();     // and its reads of the previous slab are done
+    raw_barrier();       // every wave's copies are visible
+    issue(kt + STAGES - 1, (kt + STAGES - 1) % STAGES);  // refills the buffer of slab kt - 1
+    if (!XPF) read_frags(buf, 0, 0);
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+      const int slot = ks & 1;
+      if (ks + 1 < KS)
+        read_frags(buf, ks + 1, slot ^ 1);
+      else if (XPF)
+        read_frags((kt + 1) % STAGES, 0, slot ^ 1);  // slab kt + 1 (a clamped copy at the end)
+      mfmas(slot);
+    }
+    // instruction order of one slab: copies, then (without XPF) the first
+    // fragments, then every later fragment read paired with an MFMA
+    __builtin_amdgcn_sched_group_barrier(0x020, NP * NCP, 0);
+    if (!XPF) __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
+    constexpr int LATER = XPF ? KS * NRD : (KS - 1) * NRD;
+#pragma unroll
+    for (int t = 0; t < LATER; t++) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, KS * NMF - LATER, 0);
+  }
+  wait_vmcnt<0>();  // the clamped tail copies land before the workgroup ends
+
+  store_tile<TM, TN>(C, ldc, M, N, m0 + wm0, n0 + wn0, lane, acc);
+}
+
 struct TileRow {
   rise_mode mode;
   rise_tile t;
 };
 const TileRow kTiles[] = {
     {RISE_MODE_BF16, {256, 256, 64}},   {RISE_MODE_BF16, {128, 128, 64}},
+    {RISE_MODE_BF16, {256, 256, 32}},   {RISE_MODE_BF16X3, {256, 256, 16}},
     {RISE_MODE_BF16X3, {256, 256, 32}}, {RISE_MODE_BF16X3, {128, 128, 32}},
     {RISE_MODE_BF16X6, {256, 256, 16}}, {RISE_MODE_BF16X6, {128, 128, 16}},
     {RISE_MODE_FP8, {256, 256, 128}},   {RISE_MODE_FP8, {128, 128, 128}},
@@ -364,13 +547,29 @@ const TileRow kTiles[] = {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+constexpr int kBf16Waves256 = 4;  // waves per workgroup of the 256 x 256 tiles
+
 template <int BM, int BN, int BK, int MODE>
 rise_status launch_bf16(const PackedGemm& g, hipStream_t s) {
   int tiles_m = g.Mp / BM, tiles_n = g.Np / BN;
-  hipLaunchKernelGGL((packed_bf16_kernel<BM, BN, BK, MODE>), dim3(tiles_m * tiles_n),
-                     dim3(kThreads), 0, s, g.C, g.ldc, (const uint16_t*)g.Ap,
+  constexpr int NW = BM >= 256 ? kBf16Waves256 : 4;
+  hipLaunchKernelGGL((packed_bf16_kernel<BM, BN, BK, MODE, NW>), dim3(tiles_m * tiles_n),
+                     dim3(64 * NW), 0, s, g.C, g.ldc, (const uint16_t*)g.Ap,
                      (const uint16_t*)g.Bp, g.M, g.N, g.Kp, g.Mp, g.Np, tiles_m, tiles_n);
   return check_launch("packed_bf16_kernel");
+}
+
+constexpr bool kAsyncXpf = false;
+
+template <int BM, int BN, int BK, int STAGES, int MODE>
+rise_status launch_bf16_async(const PackedGemm& g, hipStream_t s) {
+  int tiles_m = g.Mp / BM, tiles_n = g.Np / BN;
+  hipLaunchKernelGGL(
+      (packed_bf16_async_kernel<BM, BN, BK, STAGES, MODE, (kAsyncXpf && (BK / 16) % 2 == 0)>),
+                     dim3(tiles_m * tiles_n), dim3(kThreads), 0, s, g.C, g.ldc,
+                     (const uint16_t*)g.Ap, (const uint16_t*)g.Bp, g.M, g.N, g.Kp, g.Mp, g.Np,
+                     tiles_m, tiles_n);
+  return check_launch("packed_bf16_async_kernel");
 }
 
 template <int BM, int BN>
@@ -419,9 +618,11 @@ size_t gemm_lowp_workspace(int M, int N, int K, rise_mode mode, const rise_tile&
 rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStream_t s) {
   switch (g.mode) {
     case RISE_MODE_BF16:
+      if (t.bm == 256 && t.bk == 32) return launch_bf16_async<256, 256, 32, 4, RISE_MODE_BF16>(g, s);
       if (t.bm == 256) return launch_bf16<256, 256, 64, RISE_MODE_BF16>(g, s);
       return launch_bf16<128, 128, 64, RISE_MODE_BF16>(g, s);
     case RISE_MODE_BF16X3:
+      if (t.bm == 256 && t.bk == 16) return launch_bf16_async<256, 256, 16, 4, RISE_MODE_BF16X3>(g, s);
       if (t.bm == 256) return launch_bf16<256, 256, 32, RISE_MODE_BF16X3>(g, s);
       return launch_bf16<128, 128, 32, RISE_MODE_BF16X3>(g, s);
     case RISE_MODE_BF16X6:

@@ -20,6 +20,10 @@
 // the caller picks one through rise_stencil_schedule (both compute the same
 // sums in the same order).  Square windows of 1, 3, 5 and 7 use these
 // kernels; other odd sizes up to 15 use a direct per-output kernel.
+#include <stdint.h>
+
+#include <algorithm>
+
 #include "common.h"
 #include "tiles.h"
 
@@ -38,6 +42,69 @@ __global__ __launch_bounds__(kThreads) void stencil2d_tiled(
   const int lid = xcd_contiguous(blockIdx.x, gridDim.x);
   tiles::stencil_lds_tile<K, VEC, TY>(out, ld_out, in, ld_in, H, W, w, zero_pad,
                                       (lid / tiles_x) * TY, (lid % tiles_x) * TX, lds);
+}
+
+// Resident-grid pipelined schedule: the LDS halo tile above, but each
+// workgroup walks a fixed list of tiles.  Per tile: one barrier, then the
+// loads of the next tile are issued into registers, the current tile is
+// reduced from one LDS buffer into registers, the next tile is written to the
+// other LDS buffer, and only then are the current outputs stored.  The loads
+// are thus the oldest vector-memory operations when their data is needed (the
+// single vmcnt counter of gfx9 also counts stores), and HBM traffic overlaps
+// the k*k FMAs inside every workgroup (with aligned rows the fetch has no
+// branches, so no merge point forces an early wait).  The row-major tile raster is cut into 8
+// contiguous bands, one per XCD (workgroup b runs on XCD b % 8); workgroup j
+// of an XCD takes tiles j, j + per, j + 2 per, ... of its band, so the XCD's
+// workgroups sweep the band together and halo rows shared by vertically
+// adjacent tiles are read while they are still in that XCD's L2.  Output
+// stores are non-temporal.
+template <int K, bool VEC, int TY>
+__global__ __launch_bounds__(kThreads) void stencil2d_pipe(
+    float* __restrict__ out, int64_t ld_out, const float* __restrict__ in, int64_t ld_in, int H,
+    int W, const float* __restrict__ w, int zero_pad, int tiles_x, int ntiles, int per) {
+  using Cfg = tiles::StencilCfg<K, TY>;
+  __shared__ f32x4 lds[2][Cfg::LDS_CHUNKS];
+  const int xcd = blockIdx.x % kNumXcd, j = blockIdx.x / kNumXcd;
+  const int band_end = (int)((int64_t)ntiles * (xcd + 1) / kNumXcd);
+  int t = (int)((int64_t)ntiles * xcd / kNumXcd) + j;
+  if (t >= band_end) return;  // the whole workgroup leaves before any barrier
+
+  float wt[K][K];
+  tiles::stencil_weights<K>(wt, w);
+  tiles::StencilRegs<K, TY> st;
+  uint32_t mode = 0;
+  auto fetch = [&](int y0, int x0) {
+    if (VEC)
+      tiles::stencil_fetch_aligned<K, TY>(st, mode, in, ld_in, H, W, zero_pad, y0, x0);
+    else
+      tiles::stencil_fetch<K, VEC, TY>(st, in, ld_in, H, W, zero_pad, y0, x0);
+  };
+  auto stash = [&](f32x4* dst) {
+    if (VEC)
+      tiles::stencil_stash_aligned<K, TY>(st, mode, dst);
+    else
+      tiles::stencil_stash<K, TY>(st, dst);
+  };
+  int y0 = (t / tiles_x) * TY, x0 = (t % tiles_x) * TX;
+  fetch(y0, x0);
+  stash(lds[0]);
+  int buf = 0;
+  while (true) {
+    __syncthreads();  // lds[buf] is complete; every wave is done with lds[buf ^ 1]
+    const int next = t + per;
+    const bool more = next < band_end;
+    const int ny0 = (next / tiles_x) * TY, nx0 = (next % tiles_x) * TX;
+    if (more) fetch(ny0, nx0);
+    float res[TY / 4][4];
+    tiles::stencil_compute<K, TY>(res, wt, lds[buf]);
+    if (more) stash(lds[buf ^ 1]);
+    tiles::stencil_store<VEC, TY, true>(out, ld_out, H, W, res, y0, x0);
+    if (!more) break;
+    t = next;
+    y0 = ny0;
+    x0 = nx0;
+    buf ^= 1;
+  }
 }
 
 // Streaming schedule: every wave owns one 256-column strip segment of `L`
@@ -200,6 +267,32 @@ rise_status launch_tiled(const StencilArgs& a, hipStream_t s) {
   return check_launch("stencil2d_tiled");
 }
 
+// Workgroups per XCD for the pipelined schedule: as many as stay resident
+// (occupancy x CUs / 8), then evened out so that every workgroup of a band
+// gets the same number of tiles, give or take one.
+template <int K, bool VEC, int TY>
+rise_status launch_pipe(const StencilArgs& a, hipStream_t s) {
+  const int tiles_x = (a.W + TX - 1) / TX, tiles_y = (a.H + TY - 1) / TY;
+  const int64_t ntiles = (int64_t)tiles_x * tiles_y;
+  if (ntiles > INT32_MAX) return fail(RISE_ERR_SHAPE, "rise_stencil2d: too many tiles");
+  // resident workgroups per CU (a property of the kernel on gfx950)
+  static const int occ = [] {
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, stencil2d_pipe<K, VEC, TY>, kThreads, 0) !=
+            hipSuccess || o < 1)
+      o = 1;
+    return o;
+  }();
+  const int64_t band = (ntiles + kNumXcd - 1) / kNumXcd;
+  const int64_t max_per = std::max<int64_t>(1, (int64_t)occ * device_cu_count() / kNumXcd);
+  const int64_t rounds = (band + max_per - 1) / max_per;
+  const int per = (int)std::max<int64_t>(1, (band + rounds - 1) / rounds);
+  hipLaunchKernelGGL((stencil2d_pipe<K, VEC, TY>), dim3(kNumXcd * per), dim3(kThreads), 0, s,
+                     a.out, a.ld_out, a.in, a.ld_in, a.H, a.W, a.w, (int)(a.pad == RISE_PAD_ZERO),
+                     tiles_x, (int)ntiles, per);
+  return check_launch("stencil2d_pipe");
+}
+
 template <int K, bool VEC, int L>
 rise_status launch_stream(const StencilArgs& a, hipStream_t s) {
   int strips = (a.W + TX - 1) / TX, segs = (a.H + L - 1) / L;
@@ -215,6 +308,9 @@ rise_status launch_k(const StencilArgs& a, const rise_stencil_schedule& sc, hipS
   if (sc.variant == RISE_STENCIL_LDS_TILE) {
     if (sc.rows == 16) return launch_tiled<K, VEC, 16>(a, s);
     if (sc.rows == 32) return launch_tiled<K, VEC, 32>(a, s);
+  } else if (sc.variant == RISE_STENCIL_LDS_PIPE) {
+    if (sc.rows == 16) return launch_pipe<K, VEC, 16>(a, s);
+    if (sc.rows == 32) return launch_pipe<K, VEC, 32>(a, s);
   } else {
     if (sc.rows == 16) return launch_stream<K, VEC, 16>(a, s);
     if (sc.rows == 32) return launch_stream<K, VEC, 32>(a, s);
@@ -226,7 +322,8 @@ rise_status launch_k(const StencilArgs& a, const rise_stencil_schedule& sc, hipS
 
 const rise_stencil_schedule kSchedules[] = {
     {RISE_STENCIL_LDS_TILE, 16}, {RISE_STENCIL_LDS_TILE, 32}, {RISE_STENCIL_STREAM, 16},
-    {RISE_STENCIL_STREAM, 32},   {RISE_STENCIL_STREAM, 64},   {RISE_STENCIL_STREAM, 128}};
+    {RISE_STENCIL_STREAM, 32},   {RISE_STENCIL_STREAM, 64},   {RISE_STENCIL_STREAM, 128},
+    {RISE_STENCIL_LDS_PIPE, 16}, {RISE_STENCIL_LDS_PIPE, 32}};
 
 }  // namespace
 

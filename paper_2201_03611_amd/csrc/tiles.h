@@ -352,29 +352,26 @@ struct StencilCfg {
   static constexpr int R = (K - 1) / 2;
   static constexpr int ROWS = TY + 2 * R;
   static constexpr int LDS_CHUNKS = ROWS * kLChunks;
+  static constexpr int PER = (LDS_CHUNKS + kThreads - 1) / kThreads;  // chunks per thread
 };
+template <int K, int TY>
+using StencilRegs = f32x4[StencilCfg<K, TY>::PER];  // one thread's share of a halo tile
 
+// Global -> registers: the (TY + 2R) x (256 + 8) halo tile of output rows
+// [y0, y0 + TY), columns [x0, x0 + 256), with pad2D applied as index remapping.
 template <int K, bool VEC, int TY>
-__device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_t ld_out,
-                                                 const float* __restrict__ in, int64_t ld_in,
-                                                 int H, int W, const float* __restrict__ w,
-                                                 int zero_pad, int y0, int x0, f32x4* lds) {
-  constexpr int R = (K - 1) / 2;
-  constexpr int RW = TY / 4;  // output rows per wave
-  constexpr int ROWS = TY + 2 * R;
-  constexpr int TOTAL = ROWS * kLChunks;
-  constexpr int PER = (TOTAL + kThreads - 1) / kThreads;
-  auto tile = reinterpret_cast<f32x4(*)[kLChunks]>(lds);
+__device__ __forceinline__ void stencil_fetch(StencilRegs<K, TY>& st,
+                                              const float* __restrict__ in, int64_t ld_in,
+                                              int H, int W, int zero_pad, int y0, int x0) {
+  using Cfg = StencilCfg<K, TY>;
   const int tid = threadIdx.x;
-
-  f32x4 st[PER];
 #pragma unroll
-  for (int p = 0; p < PER; p++) {
+  for (int p = 0; p < Cfg::PER; p++) {
     const int c = tid + p * kThreads;
     f32x4 v = {0.f, 0.f, 0.f, 0.f};
-    if (c < TOTAL) {
+    if (c < Cfg::LDS_CHUNKS) {
       const int lr = c / kLChunks, cc = c - lr * kLChunks;
-      int gy = y0 - R + lr;
+      int gy = y0 - Cfg::R + lr;
       const int gx = x0 - kHalo + cc * 4;
       bool row_ok = true;
       if (gy < 0 || gy >= H) {
@@ -401,23 +398,77 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
     }
     st[p] = v;
   }
+}
+
+// Registers -> LDS (row-major (TY + 2R) x 66 chunks of 16 bytes).
+template <int K, int TY>
+__device__ __forceinline__ void stencil_stash(const StencilRegs<K, TY>& st,
+                                              f32x4* lds) {
+  using Cfg = StencilCfg<K, TY>;
 #pragma unroll
-  for (int p = 0; p < PER; p++) {
-    const int c = tid + p * kThreads;
-    if (c < TOTAL) {
-      const int lr = c / kLChunks;
-      tile[lr][c - lr * kLChunks] = st[p];
+  for (int p = 0; p < Cfg::PER; p++) {
+    const int c = threadIdx.x + p * kThreads;
+    if (c < Cfg::LDS_CHUNKS) lds[c] = st[p];
+  }
+}
+
+// Aligned rows (VEC): every 16-byte chunk of the halo tile is either wholly
+// inside or wholly outside the image (columns are multiples of 4 and W % 4 ==
+// 0), so the fetch can be branch-free: each chunk is loaded from a clamped,
+// always valid address, and a 2-bit mode per chunk says what pad2D makes of
+// it (0 as loaded, 1 zero, 2 the first element repeated, 3 the last element
+// repeated); the mode is applied when the chunk is written to LDS, so the
+// loads stay in flight until then.
+template <int K, int TY>
+__device__ __forceinline__ void stencil_fetch_aligned(StencilRegs<K, TY>& st, uint32_t& mode,
+                                                      const float* __restrict__ in, int64_t ld_in,
+                                                      int H, int W, int zero_pad, int y0, int x0) {
+  using Cfg = StencilCfg<K, TY>;
+  static_assert(2 * Cfg::PER <= 32, "mode bits");
+  uint32_t m_all = 0;
+#pragma unroll
+  for (int p = 0; p < Cfg::PER; p++) {
+    const int c = min((int)threadIdx.x + p * kThreads, Cfg::LDS_CHUNKS - 1);
+    const int lr = c / kLChunks, cc = c - lr * kLChunks;
+    const int gy = y0 - Cfg::R + lr, gx = x0 - kHalo + cc * 4;
+    uint32_t m = 0;
+    if (gx < 0) m = 2;
+    if (gx >= W) m = 3;
+    if (zero_pad && (m != 0 || gy < 0 || gy >= H)) m = 1;
+    const int gyc = clampi(gy, 0, H - 1), gxc = clampi(gx, 0, W - 4);
+    st[p] = *reinterpret_cast<const f32x4*>(in + (int64_t)gyc * ld_in + gxc);
+    m_all |= m << (2 * p);
+  }
+  mode = m_all;
+}
+
+template <int K, int TY>
+__device__ __forceinline__ void stencil_stash_aligned(const StencilRegs<K, TY>& st, uint32_t mode,
+                                                      f32x4* lds) {
+  using Cfg = StencilCfg<K, TY>;
+#pragma unroll
+  for (int p = 0; p < Cfg::PER; p++) {
+    const int c = threadIdx.x + p * kThreads;
+    if (c < Cfg::LDS_CHUNKS) {
+      const uint32_t m = (mode >> (2 * p)) & 3u;
+      f32x4 v = st[p];
+      if (m == 1) v = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (m == 2) v = f32x4{v.x, v.x, v.x, v.x};
+      if (m == 3) v = f32x4{v.w, v.w, v.w, v.w};
+      lds[c] = v;
     }
   }
-  __syncthreads();
+}
 
-  float wt[K][K];
-#pragma unroll
-  for (int dy = 0; dy < K; dy++)
-#pragma unroll
-    for (int dx = 0; dx < K; dx++) wt[dy][dx] = w[dy * K + dx];
-
-  const int lane = tid & 63, wave = tid >> 6;
+// LDS -> k*k weighted sums.  Wave v computes output rows [y0 + v*TY/4,
+// y0 + (v+1)*TY/4); lane l owns columns x0 + 4l .. x0 + 4l + 3.
+template <int K, int TY>
+__device__ __forceinline__ void stencil_compute(float (&res)[TY / 4][4], const float (&wt)[K][K],
+                                                const f32x4* lds) {
+  constexpr int R = (K - 1) / 2;
+  constexpr int RW = TY / 4;  // output rows per wave
+  auto tile = reinterpret_cast<const f32x4(*)[kLChunks]>(lds);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = wave * RW;
   // LDS chunk `lane` = columns x-4..x-1, lane+1 = x..x+3, lane+2 = x+4..x+7
   float win[RW + 2 * R][12];
@@ -432,10 +483,8 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
       win[j][8] = c2.x; win[j][9] = c2.y; win[j][10] = c2.z; win[j][11] = c2.w;
     }
   }
-  const int x = x0 + lane * 4;
 #pragma unroll
-  for (int o = 0; o < RW; o++) {
-    float acc[4];
+  for (int o = 0; o < RW; o++)
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       float a = 0.f;
@@ -443,20 +492,75 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
       for (int dy = 0; dy < K; dy++)
 #pragma unroll
         for (int dx = 0; dx < K; dx++) a = fmaf(win[o + dy][4 + q + dx - R], wt[dy][dx], a);
-      acc[q] = a;
+      res[o][q] = a;
     }
-    const int y = y0 + r0 + o;
+}
+
+// join: 16-byte row stores of the wave's outputs (guarded at the image edge).
+// NT selects non-temporal stores (the output is not read again by this pass).
+template <bool VEC, int TY, bool NT>
+__device__ __forceinline__ void stencil_store(float* __restrict__ out, int64_t ld_out, int H,
+                                              int W, const float (&res)[TY / 4][4], int y0,
+                                              int x0) {
+  constexpr int RW = TY / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = x0 + lane * 4;
+#pragma unroll
+  for (int o = 0; o < RW; o++) {
+    const int y = y0 + wave * RW + o;
     if (y < H) {
       float* op = out + (int64_t)y * ld_out;
       if (VEC && x + 3 < W) {
-        *reinterpret_cast<f32x4*>(op + x) = f32x4{acc[0], acc[1], acc[2], acc[3]};
+        const f32x4 v = f32x4{res[o][0], res[o][1], res[o][2], res[o][3]};
+        if (NT)
+          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(op + x));
+        else
+          *reinterpret_cast<f32x4*>(op + x) = v;
       } else {
 #pragma unroll
         for (int q = 0; q < 4; q++)
-          if (x + q < W) op[x + q] = acc[q];
+          if (x + q < W) op[x + q] = res[o][q];
       }
     }
   }
+}
+
+template <int K, bool VEC, int TY, bool NT>
+__device__ __forceinline__ void stencil_compute_store(float* __restrict__ out, int64_t ld_out,
+                                                      int H, int W, const float (&wt)[K][K],
+                                                      int y0, int x0, const f32x4* lds) {
+  float res[TY / 4][4];
+  stencil_compute<K, TY>(res, wt, lds);
+  stencil_store<VEC, TY, NT>(out, ld_out, H, W, res, y0, x0);
+}
+
+template <int K>
+__device__ __forceinline__ void stencil_weights(float (&wt)[K][K], const float* __restrict__ w) {
+#pragma unroll
+  for (int dy = 0; dy < K; dy++)
+#pragma unroll
+    for (int dx = 0; dx < K; dx++) wt[dy][dx] = w[dy * K + dx];
+}
+
+// One tile, start to finish (fetch, stage, barrier, compute, store).
+template <int K, bool VEC, int TY>
+__device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_t ld_out,
+                                                 const float* __restrict__ in, int64_t ld_in,
+                                                 int H, int W, const float* __restrict__ w,
+                                                 int zero_pad, int y0, int x0, f32x4* lds) {
+  StencilRegs<K, TY> st;
+  if (VEC) {
+    uint32_t mode;
+    stencil_fetch_aligned<K, TY>(st, mode, in, ld_in, H, W, zero_pad, y0, x0);
+    stencil_stash_aligned<K, TY>(st, mode, lds);
+  } else {
+    stencil_fetch<K, VEC, TY>(st, in, ld_in, H, W, zero_pad, y0, x0);
+    stencil_stash<K, TY>(st, lds);
+  }
+  __syncthreads();
+  float wt[K][K];
+  stencil_weights<K>(wt, w);
+  stencil_compute_store<K, VEC, TY, false>(out, ld_out, H, W, wt, y0, x0, lds);
 }
 
 }  // namespace tiles

@@ -129,6 +129,20 @@ def test_modes_integer_exact(rise, mode):
 
 
 @pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("K", [1, 16, 33, 96, 130])
+def test_modes_short_k_every_tile(rise, mode, K):
+    # fewer K slabs than the pipelines have stages, and ragged last slabs
+    g = ri.rng(40 + K)
+    M, N = 97, 260
+    A = ri.integer_matrix(g, M, K, bound=2)
+    B = ri.integer_matrix(g, K, N, bound=2)
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+    for tile in rise.rise_gemm_tiles(mode):
+        C = run(rise, A, B, mode=mode, tile=tile)
+        assert np.array_equal(C, exact), tile
+
+
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("ops", [(False, False), (True, True)])
 def test_modes_match_mode_oracle(rise, mode, ops):
     M, N, K = 333, 290, 515

@@ -43,6 +43,22 @@ def test_tiled_kernel_vs_oracle(rise, pad, H, W, k):
         assert componentwise(out, ref, scale) <= TOL_F32, sc
 
 
+@pytest.mark.parametrize("pad", list(PADS))
+@pytest.mark.parametrize("H,W", [(2050, 2100), (4099, 513)])
+@pytest.mark.parametrize("k", [3, 5, 7])
+def test_resident_grid_walks_several_tiles(rise, pad, H, W, k):
+    # more tiles than resident workgroups, so each workgroup of the pipelined
+    # schedule walks two or more tiles through both LDS buffers
+    g = ri.rng(H + W * 7 + k)
+    img = ri.uniform_matrix(g, H, W, 0.0, 1.0)
+    w = ri.uniform_matrix(g, k, k)
+    ref = oracle.stencil2d(img, w, PADS[pad])
+    scale = stencil_scale(img, w, PADS[pad])
+    for sc in [s for s in rise.rise_stencil_schedules() if s[0] != "stream"]:
+        out = run(rise, img, w, pad, sc)
+        assert componentwise(out, ref, scale) <= TOL_F32, sc
+
+
 @pytest.mark.parametrize("kh,kw", [(9, 9), (3, 7), (15, 1), (11, 5)])
 @pytest.mark.parametrize("pad", list(PADS))
 def test_direct_kernel_vs_oracle(rise, kh, kw, pad):
