@@ -9,21 +9,19 @@
 // slide2D) is an index view into an LDS halo tile, never materialised in HBM.
 //
 // Forward (and dIn, which is the same kernel on dOut with the window rotated by
-// 180 degrees and the channel roles swapped):
-//   * persistent workgroups; the whole prepared weight matrix [Cout][9*Cin]
-//     (bf16, 73.7 KB for 64 -> 64) is loaded into LDS once per workgroup;
-//   * a tile is 4 rows x 64 pixels of one image: its (4+2) x (64+2) halo is
-//     staged in LDS with 16-byte chunks XOR-swizzled by pixel so that the 32
-//     pixels a half-wave reads hit distinct banks;
-//   * wave w computes row w of the tile: 64 pixels x Cout with
-//     v_mfma_f32_32x32x16_bf16, 8 consecutive input channels per lane;
-//   * the FP32 result is rounded to bf16 and staged through LDS for 16-byte
-//     coalesced NHWC stores.
+// 180 degrees and the channel roles swapped): out^T = W' X with the prepared
+// weights as the A operand (held in registers for the whole persistent
+// workgroup) and the pixels of an LDS halo ring as the B operand; the halo is
+// copied asynchronously a few tiles ahead (see conv3x3_fwd below).
 // dW (the gradient of the weights) contracts over pixels instead: per tile the
 // dOut tile and the input halo are staged transposed (pixels contiguous, one
 // copy per horizontal tap offset so every fragment read is aligned), each
 // workgroup accumulates its share of dW^T in registers, and a fixed-order
 // reduction over workgroups finishes it.
+#include <stdint.h>
+
+#include <algorithm>
+
 #include "common.h"
 #include "conv.h"
 
@@ -31,9 +29,7 @@ namespace rise {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int TY = 4;                // output rows per forward tile (one per wave)
 constexpr int TXP = 64;              // output pixels per row of a tile
-constexpr int HR = TY + 2;           // halo rows
 constexpr int HC = TXP + 2;          // halo columns
 constexpr int TAPS = 9;
 
@@ -47,8 +43,9 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float x) {
 // dst[o][tap * I + i] = bf16(weight), with
 //   forward : o = co, i = ci, weight = w[co][ci][tap]
 //   adjoint : o = ci, i = co, weight = w[co][ci][8 - tap]   (180-degree rotation)
-__global__ void conv_prep_weights(uint16_t* __restrict__ dst, const float* __restrict__ w, int Cout,
-                                  int Cin, int adjoint) {
+__global__ void conv_prep_weights(uint16_t* __restrict__ dst, uint16_t* __restrict__ zero_page,
+                                  const float* __restrict__ w, int Cout, int Cin, int adjoint) {
+  if (blockIdx.x == 0 && threadIdx.x < 128) zero_page[threadIdx.x] = 0;  // 256 bytes
   const int n = Cout * Cin * TAPS;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     const int co = e / (Cin * TAPS), rem = e - co * Cin * TAPS, ci = rem / TAPS, tap = rem % TAPS;
@@ -77,104 +74,219 @@ __device__ __forceinline__ int wslot(int o, int k) {
   return o * KCP + (k ^ ((o >> 1) & 7));
 }
 
+// Asynchronous global -> LDS copy of 16 bytes per lane (gfx950
+// global_load_lds_dwordx4: lane i's bytes land at lds_base + 16 i), its wait,
+// and a barrier without the workgroup fence (a fence would also wait for the
+// copies in flight).  The instruction text exists only in the device pass.
+__device__ __forceinline__ void copy16_to_lds(const void* src, void* lds_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
+#endif
+}
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt field is 6 bits");
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+#endif
+}
+__device__ __forceinline__ void wait_lgkmcnt0() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#endif
+}
+__device__ __forceinline__ void raw_barrier() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_barrier" ::: "memory");
+#endif
+}
+
+// Forward layer (and dIn with the adjoint weights): out^T = W' . X as an
+// implicit GEMM with M = Cout (the prepared weights, A operand), N = pixels
+// (B operand, gathered from the LDS halo: pad2D |> slide2D as an index view)
+// and K = 9 * Cin.
+//   * persistent workgroups of 4 waves; a wave owns one cout block of 32 and
+//     NPB blocks of 32 pixels of one tile row; its weight fragments for every
+//     k-step stay in registers for the whole kernel (36 x 16 bytes per lane
+//     for 64 input channels), so only pixels are read from LDS;
+//   * a tile is TYF rows x 64 pixels of one image (TYF = 1 for 64 output
+//     channels, 2 for 32); its (TYF+2) x 66 halo is copied global -> LDS
+//     asynchronously into a ring of NBUF buffers, NBUF - 1 tiles ahead of the
+//     one being reduced; out-of-image halo pixels are fetched from a zeroed
+//     256-byte page (zero padding) or from the clamped pixel;
+//   * the waits count instructions: every tile issues the same copies (the
+//     tail re-copies the band's last tile into a free buffer) and the same
+//     stores (out-of-image outputs go to a 256-byte dump page), so "the copies
+//     of tile i+1 have landed" is a fixed vmcnt;
+//   * 16-byte chunks are XOR-swizzled by pixel (halo_slot) so the 16 pixels a
+//     lane group reads at one chunk hit distinct bank slots; the copies apply
+//     the swizzle on the global side;
+//   * the D layout gives each lane 4 consecutive output channels of a pixel
+//     per register group: rounded to bf16 and stored as 8 bytes.
 template <int CI, int CO>
-__global__ __launch_bounds__(kThreads, 1) void conv3x3_fwd(
+struct FwdCfg {
+  static constexpr int CH = CI / 8;                 // 16-byte chunks per pixel
+  static constexpr int NCB = CO / 32;               // cout blocks
+  static constexpr int NPB = 1;                     // pixel blocks per wave (registers)
+  static constexpr int WPR = NCB * (2 / NPB);       // waves per tile row
+  static constexpr int TYF = 4 / WPR;               // tile rows
+  static constexpr int KS = TAPS * CI / 16;         // k-steps of 16
+  static constexpr int SLOTS = (TYF + 2) * HC * CH; // halo chunks
+  static constexpr int NQ = (SLOTS + 63) / 64;      // wave-sized copies per tile
+  static constexpr int QPW = (NQ + 3) / 4;          // copies per wave (at most)
+  static constexpr int NBUF = 3;                    // halo ring
+  static constexpr int XPF = CI == 64 ? 3 : 4;      // fragment lookahead (k-steps)
+  static_assert(WPR * TYF == 4, "four waves per tile");
+};
+
+template <int CI, int CO>
+__global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
     uint16_t* __restrict__ out, const uint16_t* __restrict__ in,
-    const uint16_t* __restrict__ wp, int B, int H, int W, int zero_pad, int tiles_x,
-    int tiles_y, int ntiles) {
-  constexpr int CH = CI / 8;            // 16-byte chunks per halo pixel
-  constexpr int KC = TAPS * CI / 8;     // 16-byte chunks per weight row
-  constexpr int KCP = (KC + 7) / 8 * 8; // padded row in LDS
-  constexpr int NJ = CO / 32;           // 32-wide output-channel blocks
-  constexpr int HALO_CHUNKS = HR * HC * CH;
-  constexpr int STAGE_CHUNKS = TY * TXP * CO / 8;
-  constexpr int BUF = HALO_CHUNKS > STAGE_CHUNKS ? HALO_CHUNKS : STAGE_CHUNKS;
-  static_assert(CI % 16 == 0 && CO % 32 == 0, "channel counts");
-  __shared__ i32x4 wl[CO * KCP];
-  __shared__ i32x4 buf[BUF];
+    const uint16_t* __restrict__ wp, const uint16_t* __restrict__ zero_page,
+    uint16_t* __restrict__ dump_page, int B, int H, int W, int zero_pad, int tiles_x, int tiles_y,
+    int ntiles, int per) {
+  using F = FwdCfg<CI, CO>;
+  constexpr int CH = F::CH, NPB = F::NPB, NCB = F::NCB, KS = F::KS, NQ = F::NQ, QPW = F::QPW;
+  constexpr int TYF = F::TYF, NBUF = F::NBUF, DIST = NBUF - 1;
+  constexpr int NST = 4 * NPB;  // stores per wave per tile
+  __shared__ i32x4 halo[NBUF][NQ * 64];  // padded to whole copies; the tail is never read
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int il = lane & 31, kh = lane >> 5;
+  const int wrow = wave / F::WPR, rem = wave % F::WPR;
+  const int wcb = rem % NCB, wpb = rem / NCB;
 
-  for (int c = tid; c < CO * KC; c += kThreads) {
-    const int o = c / KC, k = c - o * KC;
-    wl[wslot<KCP>(o, k)] = reinterpret_cast<const i32x4*>(wp)[c];
+  const int xcd = blockIdx.x % kNumXcd, jb = blockIdx.x / kNumXcd;
+  const int band_end = (int)((int64_t)ntiles * (xcd + 1) / kNumXcd);
+  int t = (int)((int64_t)ntiles * xcd / kNumXcd) + jb;
+  if (t >= band_end) return;  // the whole workgroup leaves before any barrier
+
+  // weight fragments: lane (il, kh) holds w'[wcb*32 + il][16 ks + 8 kh .. +8]
+  bf16x8 wf[KS];
+  {
+    const uint16_t* wr = wp + (int64_t)(wcb * 32 + il) * (TAPS * CI) + 8 * kh;
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) wf[ks] = *reinterpret_cast<const bf16x8*>(wr + 16 * ks);
   }
-
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int b = t / (tiles_x * tiles_y);
-    const int rem = t - b * tiles_x * tiles_y;
-    const int ty = rem % tiles_y, tx = rem / tiles_y;  // walk down a column of tiles
-    const int y0 = ty * TY, x0 = tx * TXP;
+  // copy geometry, fixed per lane: copy q of this wave fills slots
+  // (wave + 4 q) * 64 + lane = pixel p, physical chunk pc (logical chunk pc ^ key)
+  int geo[QPW];
+#pragma unroll
+  for (int q = 0; q < QPW; q++) {
+    const int g = wave + 4 * q, sl = g * 64 + lane;
+    geo[q] = -1;
+    if (g < NQ && sl < F::SLOTS) {
+      const int p = sl / CH, pc = sl % CH;
+      const int c = pc ^ ((p / (16 / CH)) % CH);
+      geo[q] = ((p / HC) << 16) | ((p % HC) << 8) | c;
+    }
+  }
+  auto coords = [&](int tt, int& b, int& y0, int& x0) {
+    const int per_img = tiles_x * tiles_y;
+    b = tt / per_img;
+    const int r = tt - b * per_img;
+    y0 = (r / tiles_x) * TYF;
+    x0 = (r % tiles_x) * TXP;
+  };
+  auto issue = [&](int tt, int buf) {
+    int b, y0, x0;
+    coords(tt, b, y0, x0);
     const uint16_t* img = in + (int64_t)b * H * W * CI;
-    __syncthreads();  // previous tile's staging reads (and the weight stores) are done
-
-    for (int c = tid; c < HALO_CHUNKS; c += kThreads) {
-      const int p = c / CH, ch = c - p * CH;
-      const int hr = p / HC, hc = p - hr * HC;
-      int gy = y0 - 1 + hr, gx = x0 - 1 + hc;
-      i32x4 v = {0, 0, 0, 0};
-      const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
-      if (inside || !zero_pad) {
-        gy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy);
-        gx = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
-        v = reinterpret_cast<const i32x4*>(img + ((int64_t)gy * W + gx) * CI)[ch];
-      }
-      buf[halo_slot<CH>(p, ch)] = v;
-    }
-    __syncthreads();
-
-    f32x16 acc[2][NJ];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-      for (int j = 0; j < NJ; j++)
-#pragma unroll
-        for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
-
-#pragma unroll 1
-    for (int tap = 0; tap < TAPS; tap++) {
-      const int dy = tap / 3, dx = tap - dy * 3;
-#pragma unroll
-      for (int c16 = 0; c16 < CI / 16; c16++) {
-        const int ch = 2 * c16 + kh;
-        bf16x8 a[2], bb[NJ];
-#pragma unroll
-        for (int i = 0; i < 2; i++) {
-          const int p = (wave + dy) * HC + 32 * i + il + dx;
-          a[i] = __builtin_bit_cast(bf16x8, buf[halo_slot<CH>(p, ch)]);
+    for (int q = 0; q < QPW; q++) {
+      const int g = wave + 4 * q;
+      if (g < NQ) {
+        const int gq = geo[q];
+        const void* src = zero_page;
+        if (gq >= 0) {
+          int gy = y0 - 1 + (gq >> 16), gx = x0 - 1 + ((gq >> 8) & 255);
+          const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+          if (inside || !zero_pad) {
+            gy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy);
+            gx = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
+            src = img + ((int64_t)gy * W + gx) * CI + (gq & 255) * 8;
+          }
         }
-#pragma unroll
-        for (int j = 0; j < NJ; j++)
-          bb[j] = __builtin_bit_cast(bf16x8, wl[wslot<KCP>(32 * j + il, tap * CH + ch)]);
-#pragma unroll
-        for (int i = 0; i < 2; i++)
-#pragma unroll
-          for (int j = 0; j < NJ; j++)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+        copy16_to_lds(src, &halo[buf][g * 64]);
       }
     }
-    __syncthreads();  // halo no longer read: reuse it as the output staging area
+  };
 
-    uint16_t* stage = reinterpret_cast<uint16_t*>(buf);
+  // the copies of one tile by this wave (wave-uniform)
+  const bool full_copies = wave + 4 * (QPW - 1) < NQ;
+  const int last = band_end - 1;
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+  for (int d = 0; d < DIST; d++) issue(min(t + d * per, last), d);
+  wait_vmcnt<0>();  // the first tiles' copies (and the weight loads) have landed
+  int buf = 0;
+  while (true) {
+    const int next = t + per;
+    const bool more = next < band_end;
+    wait_lgkmcnt0();  // this wave's reads of the previous buffer are done
+    raw_barrier();    // every wave's copies into halo[buf] are visible
+    // refill the buffer reduced in the previous iteration, DIST tiles ahead
+    issue(min(t + DIST * per, last), (buf + DIST) % NBUF);
+
+    f32x16 acc[NPB];
 #pragma unroll
-      for (int j = 0; j < NJ; j++)
+    for (int pb = 0; pb < NPB; pb++)
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-          const int px = 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
-          stage[(wave * TXP + px) * CO + 32 * j + il] = f32_to_bf16(acc[i][j][r]);
-        }
-    __syncthreads();
-    uint16_t* dst = out + (int64_t)b * H * W * CO;
-    for (int c = tid; c < STAGE_CHUNKS; c += kThreads) {
-      const int p = c / (CO / 8), ch = c - p * (CO / 8);
-      const int ry = p / TXP, rx = p - ry * TXP;
-      const int gy = y0 + ry, gx = x0 + rx;
-      if (gy < H && gx < W)
-        reinterpret_cast<i32x4*>(dst + ((int64_t)gy * W + gx) * CO)[ch] = buf[c];
+      for (int r = 0; r < 16; r++) acc[pb][r] = 0.f;
+    // pixel fragments are read XPF k-steps ahead of their MFMA (a ring of
+    // XPF + 1 register slots): one MFMA per k-step is shorter than the LDS
+    // latency, so a one-step lookahead would stall every step
+    constexpr int XPF = F::XPF;
+    bf16x8 xf[XPF + 1][NPB];
+    auto read_x = [&](int ks, int slot) {
+      const int tap = ks / (CI / 16), c16 = ks % (CI / 16);
+      const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+      for (int pb = 0; pb < NPB; pb++) {
+        const int p = (wrow + dy) * HC + 32 * (wpb * NPB + pb) + il + dx;
+        xf[slot][pb] = __builtin_bit_cast(bf16x8, halo[buf][halo_slot<CH>(p, 2 * c16 + kh)]);
+      }
+    };
+#pragma unroll
+    for (int ks = 0; ks < XPF && ks < KS; ks++) read_x(ks, ks);
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+      if (ks + XPF < KS) read_x(ks + XPF, (ks + XPF) % (XPF + 1));
+#pragma unroll
+      for (int pb = 0; pb < NPB; pb++)
+        acc[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[ks], xf[ks % (XPF + 1)][pb], acc[pb],
+                                                          0, 0, 0);
+#pragma unroll
+      for (int pb = 0; pb < NPB; pb++) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+      }
     }
+    // the next tile's copies have landed: younger than them are the copies of
+    // DIST - 1 later tiles and the stores of DIST - 1 tiles
+    if (full_copies)
+      wait_vmcnt<(DIST - 1) * (QPW + NST)>();
+    else
+      wait_vmcnt<(DIST - 1) * (QPW - 1 + NST)>();
+
+    int b, y0, x0;
+    coords(t, b, y0, x0);
+    const int y = y0 + wrow;
+#pragma unroll
+    for (int pb = 0; pb < NPB; pb++) {
+      const int x = x0 + 32 * (wpb * NPB + pb) + il;
+      uint16_t* dst = (y < H && x < W)
+                          ? out + (((int64_t)b * H + y) * W + x) * CO + wcb * 32 + 4 * kh
+                          : dump_page + 4 * kh;
+#pragma unroll
+      for (int g = 0; g < 4; g++) {
+        const uint32_t lo = f32_to_bf16(acc[pb][4 * g]) | ((uint32_t)f32_to_bf16(acc[pb][4 * g + 1]) << 16);
+        const uint32_t hi = f32_to_bf16(acc[pb][4 * g + 2]) | ((uint32_t)f32_to_bf16(acc[pb][4 * g + 3]) << 16);
+        *reinterpret_cast<uint2*>(dst + 8 * g) = uint2{lo, hi};
+      }
+    }
+    if (!more) break;
+    t = next;
+    buf = (buf + 1) % NBUF;
   }
 }
 
@@ -313,13 +425,27 @@ int dw_blocks(int B, int H, int W) {
 }
 
 template <int CI, int CO>
-rise_status launch_fwd(uint16_t* out, const uint16_t* in, const uint16_t* wp, int B, int H, int W,
+rise_status launch_fwd(uint16_t* out, const uint16_t* in, const uint16_t* wp,
+                       const uint16_t* zero_page, uint16_t* dump_page, int B, int H, int W,
                        int zero, hipStream_t s) {
-  const int tiles_x = (W + TXP - 1) / TXP, tiles_y = (H + TY - 1) / TY;
-  const int ntiles = B * tiles_x * tiles_y;
-  const int grid = ntiles < 256 ? ntiles : 256;
-  hipLaunchKernelGGL((conv3x3_fwd<CI, CO>), dim3(grid), dim3(kThreads), 0, s, out, in, wp, B, H, W,
-                     zero, tiles_x, tiles_y, ntiles);
+  constexpr int TYF = FwdCfg<CI, CO>::TYF;
+  const int tiles_x = (W + TXP - 1) / TXP, tiles_y = (H + TYF - 1) / TYF;
+  const int64_t ntiles = (int64_t)B * tiles_x * tiles_y;
+  if (ntiles > INT32_MAX) return fail(RISE_ERR_SHAPE, "conv: too many tiles");
+  // workgroups per XCD: as many as stay resident, evened out over the band
+  static const int occ = [] {
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, conv3x3_fwd<CI, CO>, kThreads, 0) !=
+            hipSuccess || o < 1)
+      o = 1;
+    return o;
+  }();
+  const int64_t band = (ntiles + kNumXcd - 1) / kNumXcd;
+  const int64_t max_per = std::max<int64_t>(1, (int64_t)occ * device_cu_count() / kNumXcd);
+  const int64_t rounds = (band + max_per - 1) / max_per;
+  const int per = (int)std::max<int64_t>(1, (band + rounds - 1) / rounds);
+  hipLaunchKernelGGL((conv3x3_fwd<CI, CO>), dim3(kNumXcd * per), dim3(kThreads), 0, s, out, in,
+                     wp, zero_page, dump_page, B, H, W, zero, tiles_x, tiles_y, (int)ntiles, per);
   return check_launch("conv3x3_fwd");
 }
 
@@ -334,10 +460,13 @@ rise_status launch_dw(float* partial, const uint16_t* dout, const uint16_t* in, 
   return check_launch("conv3x3_dw");
 }
 
-rise_status fwd_dispatch(uint16_t* out, const uint16_t* in, const uint16_t* wp, int B, int CI,
-                         int CO, int H, int W, int zero, hipStream_t s) {
+rise_status fwd_dispatch(uint16_t* out, const uint16_t* in, const uint16_t* wp, void* pages,
+                         int B, int CI, int CO, int H, int W, int zero, hipStream_t s) {
+  const uint16_t* zero_page = (const uint16_t*)pages;
+  uint16_t* dump_page = (uint16_t*)((char*)pages + 256);
 #define RISE_CONV_CASE(I, O) \
-  if (CI == I && CO == O) return launch_fwd<I, O>(out, in, wp, B, H, W, zero, s);
+  if (CI == I && CO == O)    \
+    return launch_fwd<I, O>(out, in, wp, zero_page, dump_page, B, H, W, zero, s);
   RISE_CONV_CASE(16, 32) RISE_CONV_CASE(16, 64) RISE_CONV_CASE(32, 32)
   RISE_CONV_CASE(32, 64) RISE_CONV_CASE(64, 32) RISE_CONV_CASE(64, 64)
 #undef RISE_CONV_CASE
@@ -368,31 +497,37 @@ bool conv_supported(int Cin, int Cout, int kh, int kw, bool backward) {
   return din_ok && dw_ok;
 }
 
-size_t conv_forward_workspace(int Cin, int Cout) { return round256((size_t)Cout * TAPS * Cin * 2); }
+// workspace: [prepared bf16 weights | 256-byte zero page | 256-byte dump page |
+//             dW partials (backward)]
+size_t conv_forward_workspace(int Cin, int Cout) {
+  return round256((size_t)Cout * TAPS * Cin * 2) + 512;
+}
 
 size_t conv_backward_workspace(int B, int Cin, int Cout, int H, int W) {
-  return round256((size_t)Cout * TAPS * Cin * 2) +
-         (size_t)dw_blocks(B, H, W) * Cout * TAPS * Cin * 4;
+  return conv_forward_workspace(Cin, Cout) + (size_t)dw_blocks(B, H, W) * Cout * TAPS * Cin * 4;
 }
 
 rise_status launch_conv2d(const ConvArgs& a, void* ws, hipStream_t s) {
   uint16_t* wp = (uint16_t*)ws;
-  hipLaunchKernelGGL(conv_prep_weights, dim3(64), dim3(kThreads), 0, s, wp, a.w, a.Cout, a.Cin, 0);
+  uint16_t* zp = (uint16_t*)((char*)ws + round256((size_t)a.Cout * TAPS * a.Cin * 2));
+  hipLaunchKernelGGL(conv_prep_weights, dim3(64), dim3(kThreads), 0, s, wp, zp, a.w, a.Cout, a.Cin,
+                     0);
   rise_status st = check_launch("conv_prep_weights");
   if (st != RISE_OK) return st;
-  return fwd_dispatch(a.out, a.in, wp, a.B, a.Cin, a.Cout, a.H, a.W, a.zero_pad, s);
+  return fwd_dispatch(a.out, a.in, wp, zp, a.B, a.Cin, a.Cout, a.H, a.W, a.zero_pad, s);
 }
 
 rise_status launch_conv2d_backward(const ConvBwdArgs& a, void* ws, hipStream_t s) {
   uint16_t* wp = (uint16_t*)ws;
-  float* partial = (float*)((char*)ws + round256((size_t)a.Cout * TAPS * a.Cin * 2));
+  uint16_t* zp = (uint16_t*)((char*)ws + round256((size_t)a.Cout * TAPS * a.Cin * 2));
+  float* partial = (float*)((char*)ws + conv_forward_workspace(a.Cin, a.Cout));
   rise_status st = RISE_OK;
   if (a.din) {
     // dIn = the layer with dOut as input, channel roles swapped and the window rotated
-    hipLaunchKernelGGL(conv_prep_weights, dim3(64), dim3(kThreads), 0, s, wp, a.w, a.Cout, a.Cin,
-                       1);
+    hipLaunchKernelGGL(conv_prep_weights, dim3(64), dim3(kThreads), 0, s, wp, zp, a.w, a.Cout,
+                       a.Cin, 1);
     if ((st = check_launch("conv_prep_weights")) != RISE_OK) return st;
-    st = fwd_dispatch(a.din, a.dout, wp, a.B, a.Cout, a.Cin, a.H, a.W, 1, s);
+    st = fwd_dispatch(a.din, a.dout, wp, zp, a.B, a.Cout, a.Cin, a.H, a.W, 1, s);
     if (st != RISE_OK) return st;
   }
   if (a.dw) {
