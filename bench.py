@@ -152,8 +152,10 @@ def main():
     value = (flops_gemm + flops_sten) / (ms_step * 1e-3) / 1e12
 
     gemm_traffic = traffic_for("gemm_f32_kernel", ["paper_2201_03611_amd/csrc/gemm_f32.hip",
+                                                   "paper_2201_03611_amd/csrc/tiles.h",
                                                    "paper_2201_03611_amd/csrc/common.h"])
     sten_traffic = traffic_for("stencil2d_tiled", ["paper_2201_03611_amd/csrc/stencil.hip",
+                                                   "paper_2201_03611_amd/csrc/tiles.h",
                                                    "paper_2201_03611_amd/csrc/common.h"])
     result = {
         "metric": "GEMM TFLOP/s + stencil GB/s vs roofline; BF16-comp vs FP32 speedup at equal error",

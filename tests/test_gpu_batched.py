@@ -138,7 +138,7 @@ def test_small_mixed_batch_and_graph_replays(rise):
             check_stencil(p, host(p["dOut"]))
     for i, p in enumerate(gemms):
         bm, bn, bk = plan.tile(i)
-        assert bm in (64, 128) and bn in (64, 128) and bk == 32
+        assert bm in (64, 128) and bn in (64, 128) and bk in (16, 32)
     plan.destroy()
 
 

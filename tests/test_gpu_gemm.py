@@ -78,6 +78,35 @@ def test_unaligned_leading_dimension_uses_scalar_loads(rise):
         np.ascontiguousarray(A), B)) <= TOL_F32
 
 
+@pytest.mark.parametrize("ops", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("M,N,K", [(70, 50, 45), (130, 257, 131), (5, 3, 2)])
+def test_padded_rows_ragged_edges_every_tile(rise, ops, M, N, K):
+    # 16-byte rows (leading dimensions multiples of 4) with ragged M, N, K: the
+    # vector loads reach into each row's padding, which holds NaN here, so any
+    # element read past the operand and not zeroed would poison the result
+    import torch
+
+    g = ri.rng(M + N + K + 7 * ops[0] + 11 * ops[1])
+    A = ri.uniform_matrix(g, M, K)
+    B = ri.uniform_matrix(g, K, N)
+
+    def padded(X):
+        r, c = X.shape
+        P = np.full((r, (c + 3) // 4 * 4 + 4), np.nan, np.float32)
+        P[:, :c] = X
+        return P
+
+    As = padded(np.ascontiguousarray(A.T) if ops[0] else A)
+    Bs = padded(np.ascontiguousarray(B.T) if ops[1] else B)
+    dA, dB = dev(As), dev(Bs)
+    ref = oracle.gemm(A, B)
+    for tile in rise.rise_gemm_tiles("f32"):
+        C = torch.empty((M, N), device="cuda", dtype=torch.float32)
+        rise.rise_gemm(C, dA, dB, M, N, K, lda=As.shape[1], ldb=Bs.shape[1], ldc=N,
+                       opA=int(ops[0]), opB=int(ops[1]), tile=tile)
+        assert componentwise(host(C), ref, gemm_scale(A, B)) <= TOL_F32, tile
+
+
 def test_k_zero_writes_zero(rise):
     import torch
 
