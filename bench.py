@@ -190,6 +190,7 @@ def main():
     if not args.no_extra:
         result["batched"] = batched_leg(rise, ri, torch, dev, stream)
         result["layer"] = layer_leg(rise, torch, dev, stream)
+        result["gemv"] = gemv_leg(rise, torch, dev, stream)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(ri, np, A, B, img, wts, value, ms_step)
     print(json.dumps(result), flush=True)
@@ -345,6 +346,29 @@ def batched_leg(rise, ri, torch, dev, stream):
                    "library's default tiles (FP32 set only; the bf16 set needs its operand "
                    "preparation per call)")
     return out
+
+
+def gemv_leg(rise, torch, dev, stream):
+    """The paper's matrix-vector program at 16384 x 16384 FP32 (1 GiB of A, read
+    once per call): HBM GB/s against the 8 TB/s peak, both storage orders."""
+    n = 16384
+    g = torch.Generator(device=dev)
+    g.manual_seed(1200)
+    A = torch.rand((n, n), device=dev, generator=g) * 2 - 1
+    x = torch.rand((n,), device=dev, generator=g) * 2 - 1
+    y = torch.empty(n, device=dev)
+    res = {}
+    for name, op in (("row_major", rise.RISE_OP_N), ("transposed", rise.RISE_OP_T)):
+        nws = rise.rise_gemv_workspace(n, n, op)
+        ws = torch.empty(max(nws, 1), device=dev, dtype=torch.uint8)
+        ms = event_ms(torch, stream, lambda: rise.rise_gemv(y, A, x, n, n, lda=n, opA=op, ws=ws,
+                                                            stream=stream), 20)
+        gbs = 4.0 * n * n / (ms * 1e-3) / 1e9
+        res[name] = {"us": round(ms * 1e3, 1), "gbps": round(gbs, 1),
+                     "frac_hbm_peak": round(gbs / PEAK_HBM, 3)}
+    del A
+    torch.cuda.empty_cache()
+    return res
 
 
 def layer_leg(rise, torch, dev, stream):

@@ -115,6 +115,22 @@ rise_status rise_gemm(float* C, int64_t ldc, const void* A, rise_dtype tA, int64
                       int64_t M, int64_t N, int64_t K, rise_mode mode, const rise_tile* tile,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* Matrix-vector product, the paper's running example (Sec. IV):
+ *   y = A |> map(row => zip(row, x) |> map(*) |> reduce(+, 0))
+ * y: M floats (device); A: M x K FP32 read through opA (RISE_OP_N: stored
+ * M x K row-major, element (i,k) at A[i*lda + k], the layout of the paper's
+ * generated kernel; RISE_OP_T: stored K x M, element (i,k) at A[k*lda + i]);
+ * x: K floats.  FP32 arithmetic, the reduction order is the library's (any
+ * order is a correct reduce).  K = 0 writes y = 0; M = 0 is a no-op.
+ * Workspace: rise_gemv_workspace(M, K, opA) bytes (0 for RISE_OP_N; split-K
+ * partials for RISE_OP_T), 256-byte aligned; ws may be NULL when that is 0.
+ * Errors: NULL pointers, negative or too large sizes, lda below the stored
+ * row length, y overlapping A or x, a short, misaligned or overlapping
+ * workspace return a status and enqueue nothing. */
+size_t rise_gemv_workspace(int64_t M, int64_t K, rise_op opA);
+rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const float* x,
+                      int64_t M, int64_t K, void* ws, size_t ws_bytes, void* stream);
+
 /* Gradients of L(C) with C = A . B (A: M x K, B: K x N, row-major FP32):
  *   dA = dC . transpose(B)   (M x K)     dB = transpose(A) . dC   (K x N)
  * written as two GEMMs that read transpose views of the stored operands (no

@@ -96,6 +96,19 @@ def rise_gemm(C, A, B, M, N, K, *, lda, ldb, ldc, opA=RISE_OP_N, opB=RISE_OP_N, 
     _check(st, "rise_gemm")
 
 
+def rise_gemv_workspace(M, K, opA=RISE_OP_N):
+    return int(lib.rise_gemv_workspace(M, K, opA))
+
+
+def rise_gemv(y, A, x, M, K, *, lda, opA=RISE_OP_N, ws=None, stream=None):
+    """y (M floats) = A . x, A read through opA (the paper's matrix-vector program)."""
+    _require_cuda(y, A, x, ws)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    st = lib.rise_gemv(_ptr(y), _ptr(A), lda, opA, _ptr(x), M, K, _ptr(ws), ws_bytes,
+                       _stream(stream))
+    _check(st, "rise_gemv")
+
+
 def rise_gemm_backward_workspace(M, N, K, mode):
     return int(lib.rise_gemm_backward_workspace(M, N, K, _mode(mode)))
 
@@ -283,6 +296,19 @@ def gemm(A, B, *, transA=False, transB=False, mode="f32", tile=None, out=None, w
               opA=RISE_OP_T if transA else RISE_OP_N, opB=RISE_OP_T if transB else RISE_OP_N,
               mode=mode, tile=tile, ws=ws, stream=stream)
     return out
+
+
+def gemv(A, x, *, transA=False, out=None, stream=None):
+    """y = A . x for a 2-D float32 device tensor A (read transposed if transA) and a
+    vector x; allocates y and the workspace with torch."""
+    _require_cuda(A, x)
+    M, K = (A.shape[1], A.shape[0]) if transA else A.shape
+    op = RISE_OP_T if transA else RISE_OP_N
+    y = out if out is not None else torch.empty(M, device=A.device, dtype=torch.float32)
+    n = rise_gemv_workspace(M, K, op)
+    ws = torch.empty(n, device=A.device, dtype=torch.uint8) if n else None
+    rise_gemv(y, A, x, M, K, lda=A.stride(0), opA=op, ws=ws, stream=stream)
+    return y
 
 
 def stencil2d(img, w, pad="clamp", out=None, schedule=None, stream=None):

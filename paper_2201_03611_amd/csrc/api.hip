@@ -225,6 +225,42 @@ rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t 
   return launch_stencil2d(a, sc, (hipStream_t)stream);
 }
 
+size_t rise_gemv_workspace(int64_t M, int64_t K, rise_op opA) {
+  if (!dim_ok(M) || !dim_ok(K) || (opA != RISE_OP_N && opA != RISE_OP_T)) return 0;
+  const size_t b = gemv_workspace(M, K, opA == RISE_OP_T);
+  return (b + 255) / 256 * 256;
+}
+
+rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const float* x,
+                      int64_t M, int64_t K, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!dim_ok(M) || !dim_ok(K)) return fail(RISE_ERR_SHAPE, "rise_gemv: sizes must be in [0, 2^31)");
+  if (opA != RISE_OP_N && opA != RISE_OP_T) return fail(RISE_ERR_UNSUPPORTED, "rise_gemv: opA");
+  if (M == 0) return RISE_OK;
+  if (!y) return fail(RISE_ERR_NULL, "rise_gemv: y is NULL");
+  const int64_t ar = opA == RISE_OP_N ? M : K, ac = opA == RISE_OP_N ? K : M;
+  const Range ry = span(y, 1, M, M, 4);
+  if (K > 0) {
+    if (!A || !x) return fail(RISE_ERR_NULL, "rise_gemv: A or x is NULL");
+    if (lda < ac) return fail(RISE_ERR_SHAPE, "rise_gemv: lda below the stored row length");
+    if (overlaps(ry, span(A, ar, ac, lda, 4)) || overlaps(ry, span(x, 1, K, K, 4)))
+      return fail(RISE_ERR_ALIAS, "rise_gemv: y overlaps A or x");
+  }
+  const size_t need = gemv_workspace(M, K, opA == RISE_OP_T);
+  if (need > 0) {
+    if (!ws || ws_bytes < need)
+      return fail(RISE_ERR_WORKSPACE, "rise_gemv: workspace below rise_gemv_workspace()");
+    if ((uintptr_t)ws & 255)
+      return fail(RISE_ERR_WORKSPACE, "rise_gemv: workspace must be 256-byte aligned");
+    const Range rw{(uintptr_t)ws, (uintptr_t)ws + need};
+    if (overlaps(rw, ry) || overlaps(rw, span(A, ar, ac, lda, 4)) ||
+        overlaps(rw, span(x, 1, K, K, 4)))
+      return fail(RISE_ERR_ALIAS, "rise_gemv: workspace overlaps y, A or x");
+  }
+  GemvArgs a{y, A, lda, opA == RISE_OP_T, x, (int)M, (int)K};
+  return launch_gemv(a, ws, (hipStream_t)stream);
+}
+
 size_t rise_gemm_backward_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode) {
   size_t a = rise_gemm_workspace(M, K, N, mode, nullptr);  // dA: M x K, reduction over N
   size_t b = rise_gemm_workspace(K, N, M, mode, nullptr);  // dB: K x N, reduction over M

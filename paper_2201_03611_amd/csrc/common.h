@@ -99,6 +99,20 @@ struct StencilBwdArgs {
   int pad;
 };
 size_t stencil_backward_workspace(int H, int W, int kh, int kw);
+
+// ---------------------------------------------------------------------------
+// matrix-vector product (gemv.hip)
+// ---------------------------------------------------------------------------
+struct GemvArgs {
+  float* y;
+  const float* A;
+  int64_t lda;
+  bool trans;  // A stored K x M, read through transpose
+  const float* x;
+  int M, K;
+};
+size_t gemv_workspace(int64_t M, int64_t K, bool trans);
+rise_status launch_gemv(const GemvArgs& a, void* ws, hipStream_t s);
 rise_status launch_stencil2d_backward(const StencilBwdArgs& a, void* ws, hipStream_t s);
 
 }  // namespace rise

@@ -1,0 +1,221 @@
+// Matrix-vector product, the paper's running example (Sec. IV):
+//
+//   y = A |> map(row => zip(row, x) |> map(*) |> reduce(+, 0))
+//
+// It reads every element of A once and does one multiply-add per element, so it
+// is bound by HBM bandwidth (0.5 flop per byte), not by arithmetic: the kernels
+// are organised around coalesced 16-byte loads and enough loads in flight.
+//
+//   A row-major (the paper's layout, RISE_OP_N): a wavefront owns 4 rows at a
+//     time (map over rows -> waves, as the generated kernel's work-items own
+//     rows); its lanes stride along the rows in 16-byte chunks (split of the
+//     row into lane-sized pieces), each chunk of x is loaded once for the 4
+//     rows, and the per-lane partial sums are combined across the wavefront
+//     (the reduce, as a tree over the 64 lanes);
+//   A read through transpose (RISE_OP_T, A stored K x M): a thread owns 4
+//     consecutive outputs and sweeps rows of the stored A with 16-byte loads;
+//     K is split over workgroups when there are too few column blocks to fill
+//     the GPU, and a second kernel sums the split-K partials in a fixed order.
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace rise {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRowsPerWave = 4;
+constexpr int kColsPerBlock = kThreads * 4;  // outputs per workgroup (RISE_OP_T)
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void gemv_rows(float* __restrict__ y,
+                                                      const float* __restrict__ A, int64_t lda,
+                                                      const float* __restrict__ x, int M, int K,
+                                                      int64_t row_groups) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
+  for (int64_t g = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); g < row_groups;
+       g += nwaves) {
+    const int r0 = (int)(g * kRowsPerWave);
+    const float* rows[kRowsPerWave];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; j++)  // rows past M repeat the last row; never stored
+      rows[j] = A + (int64_t)min(r0 + j, M - 1) * lda;
+    float acc[kRowsPerWave] = {0.f, 0.f, 0.f, 0.f};
+    int k_done = 0;
+    if (VEC) {
+      const int nchunk = K / 4;
+      f32x4 a4[kRowsPerWave];
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; j++) a4[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      int c = lane;
+      // two chunks per lane per iteration keep more loads in flight
+      for (; c + 64 < nchunk; c += 128) {
+        const f32x4 x0 = reinterpret_cast<const f32x4*>(x)[c];
+        const f32x4 x1 = reinterpret_cast<const f32x4*>(x)[c + 64];
+        f32x4 v0[kRowsPerWave], v1[kRowsPerWave];
+#pragma unroll
+        for (int j = 0; j < kRowsPerWave; j++) {
+          v0[j] = reinterpret_cast<const f32x4*>(rows[j])[c];
+          v1[j] = reinterpret_cast<const f32x4*>(rows[j])[c + 64];
+        }
+#pragma unroll
+        for (int j = 0; j < kRowsPerWave; j++) {
+          a4[j].x = fmaf(v0[j].x, x0.x, a4[j].x);
+          a4[j].y = fmaf(v0[j].y, x0.y, a4[j].y);
+          a4[j].z = fmaf(v0[j].z, x0.z, a4[j].z);
+          a4[j].w = fmaf(v0[j].w, x0.w, a4[j].w);
+          a4[j].x = fmaf(v1[j].x, x1.x, a4[j].x);
+          a4[j].y = fmaf(v1[j].y, x1.y, a4[j].y);
+          a4[j].z = fmaf(v1[j].z, x1.z, a4[j].z);
+          a4[j].w = fmaf(v1[j].w, x1.w, a4[j].w);
+        }
+      }
+      for (; c < nchunk; c += 64) {
+        const f32x4 x0 = reinterpret_cast<const f32x4*>(x)[c];
+#pragma unroll
+        for (int j = 0; j < kRowsPerWave; j++) {
+          const f32x4 v = reinterpret_cast<const f32x4*>(rows[j])[c];
+          a4[j].x = fmaf(v.x, x0.x, a4[j].x);
+          a4[j].y = fmaf(v.y, x0.y, a4[j].y);
+          a4[j].z = fmaf(v.z, x0.z, a4[j].z);
+          a4[j].w = fmaf(v.w, x0.w, a4[j].w);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; j++) acc[j] = (a4[j].x + a4[j].y) + (a4[j].z + a4[j].w);
+      k_done = nchunk * 4;
+    }
+    for (int k = k_done + lane; k < K; k += 64) {  // scalar path / ragged tail
+      const float xv = x[k];
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; j++) acc[j] = fmaf(rows[j][k], xv, acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; j++) {
+      const float s = wave_sum(acc[j]);
+      if (lane == 0 && r0 + j < M) y[r0 + j] = s;
+    }
+  }
+}
+
+// out[kc * ldo + m] = sum over k in chunk kc of A[k][m] * x[k]
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void gemv_cols(float* __restrict__ out, int64_t ldo,
+                                                      const float* __restrict__ A, int64_t lda,
+                                                      const float* __restrict__ x, int M, int K,
+                                                      int mblocks, int kchunk) {
+  const int mb = blockIdx.x % mblocks, kc = blockIdx.x / mblocks;
+  const int m = mb * kColsPerBlock + threadIdx.x * 4;
+  const int k0 = kc * kchunk, k1 = min(K, k0 + kchunk);
+  if (m >= M) return;  // no barriers in this kernel
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (VEC && m + 3 < M) {
+    int k = k0;
+    for (; k + 1 < k1; k += 2) {
+      const f32x4 a0 = *reinterpret_cast<const f32x4*>(A + (int64_t)k * lda + m);
+      const f32x4 a1 = *reinterpret_cast<const f32x4*>(A + (int64_t)(k + 1) * lda + m);
+      const float x0 = x[k], x1 = x[k + 1];
+      acc.x = fmaf(a0.x, x0, acc.x); acc.y = fmaf(a0.y, x0, acc.y);
+      acc.z = fmaf(a0.z, x0, acc.z); acc.w = fmaf(a0.w, x0, acc.w);
+      acc.x = fmaf(a1.x, x1, acc.x); acc.y = fmaf(a1.y, x1, acc.y);
+      acc.z = fmaf(a1.z, x1, acc.z); acc.w = fmaf(a1.w, x1, acc.w);
+    }
+    for (; k < k1; k++) {
+      const f32x4 a0 = *reinterpret_cast<const f32x4*>(A + (int64_t)k * lda + m);
+      const float x0 = x[k];
+      acc.x = fmaf(a0.x, x0, acc.x); acc.y = fmaf(a0.y, x0, acc.y);
+      acc.z = fmaf(a0.z, x0, acc.z); acc.w = fmaf(a0.w, x0, acc.w);
+    }
+    *reinterpret_cast<f32x4*>(out + (int64_t)kc * ldo + m) = acc;
+    return;
+  }
+  float a[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int k = k0; k < k1; k++) {
+    const float x0 = x[k];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+      if (m + q < M) a[q] = fmaf(A[(int64_t)k * lda + m + q], x0, a[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; q++)
+    if (m + q < M) out[(int64_t)kc * ldo + m + q] = a[q];
+}
+
+__global__ void gemv_reduce(float* __restrict__ y, const float* __restrict__ part, int M,
+                            int nparts) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  float s = 0.f;
+  for (int p = 0; p < nparts; p++) s += part[(int64_t)p * M + m];  // fixed order
+  y[m] = s;
+}
+
+struct ColSplit {
+  int mblocks, kchunks, kchunk;
+};
+ColSplit col_split(int64_t M, int64_t K) {
+  ColSplit c;
+  c.mblocks = (int)((M + kColsPerBlock - 1) / kColsPerBlock);
+  // about 2048 workgroups in all, chunks of at least 64 rows of A
+  int64_t want = (2048 + c.mblocks - 1) / c.mblocks;
+  int64_t most = std::max<int64_t>(1, (K + 63) / 64);
+  c.kchunks = (int)std::max<int64_t>(1, std::min(want, most));
+  c.kchunk = (int)((K + c.kchunks - 1) / c.kchunks);
+  if (c.kchunk == 0) c.kchunk = 1;
+  c.kchunks = (int)std::max<int64_t>(1, (K + c.kchunk - 1) / c.kchunk);
+  return c;
+}
+
+}  // namespace
+
+size_t gemv_workspace(int64_t M, int64_t K, bool trans) {
+  if (!trans || M == 0 || K == 0) return 0;
+  const ColSplit c = col_split(M, K);
+  return c.kchunks > 1 ? (size_t)c.kchunks * M * 4 : 0;
+}
+
+rise_status launch_gemv(const GemvArgs& a, void* ws, hipStream_t s) {
+  // K = 0 needs no special case: the kernels reduce over an empty range and
+  // store the initial value 0
+  auto aligned = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  if (!a.trans) {
+    const bool vec = aligned(a.A) && aligned(a.x) && a.lda % 4 == 0;
+    const int64_t groups = (a.M + kRowsPerWave - 1) / kRowsPerWave;
+    const int64_t blocks =
+        std::min<int64_t>((groups + 3) / 4, (int64_t)device_cu_count() * 8);
+    if (vec)
+      hipLaunchKernelGGL(gemv_rows<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a.y, a.A,
+                         a.lda, a.x, a.M, a.K, groups);
+    else
+      hipLaunchKernelGGL(gemv_rows<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a.y,
+                         a.A, a.lda, a.x, a.M, a.K, groups);
+    return check_launch("gemv_rows");
+  }
+  const ColSplit c = col_split(a.M, a.K);
+  const bool vec = aligned(a.A) && a.lda % 4 == 0;
+  float* out = c.kchunks > 1 ? (float*)ws : a.y;
+  const int64_t ldo = a.M;
+  const unsigned grid = (unsigned)((int64_t)c.mblocks * c.kchunks);
+  if (vec)
+    hipLaunchKernelGGL(gemv_cols<true>, dim3(grid), dim3(kThreads), 0, s, out, ldo, a.A, a.lda,
+                       a.x, a.M, a.K, c.mblocks, c.kchunk);
+  else
+    hipLaunchKernelGGL(gemv_cols<false>, dim3(grid), dim3(kThreads), 0, s, out, ldo, a.A, a.lda,
+                       a.x, a.M, a.K, c.mblocks, c.kchunk);
+  rise_status st = check_launch("gemv_cols");
+  if (st != RISE_OK || c.kchunks == 1) return st;
+  hipLaunchKernelGGL(gemv_reduce, dim3((unsigned)((a.M + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, a.y, (const float*)ws, a.M, c.kchunks);
+  return check_launch("gemv_reduce");
+}
+
+}  // namespace rise

@@ -74,6 +74,28 @@ def test_gemm_rejections(lib):
     assert lib.rise_last_error() != b""
 
 
+def gemv(lib, y=FAKE_C, A=FAKE_A, lda=64, opA=0, x=FAKE_B, M=64, K=64, ws=None, ws_bytes=0):
+    return lib.rise_gemv(y, A, lda, opA, x, M, K, ws, ws_bytes, None)
+
+
+def test_gemv_rejections(lib):
+    assert gemv(lib, y=None) == 1                       # NULL
+    assert gemv(lib, x=None) == 1
+    assert gemv(lib, M=-1) == 2                         # SHAPE
+    assert gemv(lib, K=1 << 31) == 2
+    assert gemv(lib, lda=63) == 2
+    assert gemv(lib, opA=1, M=100, lda=99) == 2         # stored K x M needs lda >= M
+    assert gemv(lib, y=FAKE_A + 128) == 3               # ALIAS: y inside A
+    assert gemv(lib, opA=3) == 5                        # UNSUPPORTED
+    need = lib.rise_gemv_workspace(64, 100000, 1)
+    assert need > 0 and lib.rise_gemv_workspace(64, 100000, 0) == 0
+    assert gemv(lib, opA=1, K=100000) == 6              # WORKSPACE missing
+    assert gemv(lib, opA=1, K=100000, ws=0x50000000, ws_bytes=need - 1) == 6
+    assert gemv(lib, opA=1, K=100000, ws=0x50000010, ws_bytes=need) == 6
+    assert gemv(lib, opA=1, K=100000, ws=FAKE_A, ws_bytes=need) == 3
+    assert gemv(lib, M=0, y=None) == 0                  # no-op
+
+
 def test_gemm_degenerate_sizes_are_noops(lib):
     assert gemm(lib, M=0) == 0
     assert gemm(lib, N=0, C=None) == 0
