@@ -42,12 +42,12 @@ def parse():
     p.add_argument("--no-precision", action="store_true", help="skip the 8192^3 precision leg")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     p.add_argument("--no-extra", action="store_true",
-                   help="skip the batched and stencil-layer legs")
+                   help="skip the batched, stencil-layer, GEMV and iterate legs")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     p.add_argument("--only", default=None,
                    choices=["gemm_f32", "gemm_bf16", "gemm_bf16x3", "gemm_fp8", "stencil",
-                            "conv_fwd", "conv_bwd", "batched"],
+                            "conv_fwd", "conv_bwd", "batched", "gemv", "gemv_t", "iterate_sum"],
                    help="run one kernel of the path --reps times (for profilers) and exit")
     p.add_argument("--reps", type=int, default=5)
     return p.parse_args()
@@ -191,6 +191,7 @@ def main():
         result["batched"] = batched_leg(rise, ri, torch, dev, stream)
         result["layer"] = layer_leg(rise, torch, dev, stream)
         result["gemv"] = gemv_leg(rise, torch, dev, stream)
+        result["iterate_sum"] = iterate_leg(rise, torch, dev, stream)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(ri, np, A, B, img, wts, value, ms_step)
     print(json.dumps(result), flush=True)
@@ -233,6 +234,21 @@ def run_only(what, reps, rise, ri, torch, dev, stream):
                              dtype=torch.uint8)
             call = lambda i: rise.rise_conv2d_backward(dIn, dW, dout, x, w, Bn, C, C, Hc, Wc,
                                                        ws=ws, stream=stream)
+    elif what in ("gemv", "gemv_t"):
+        n = 16384
+        A = torch.rand((n, n), device=dev, generator=g) * 2 - 1
+        x = torch.rand((n,), device=dev, generator=g) * 2 - 1
+        y = torch.empty(n, device=dev)
+        op = rise.RISE_OP_T if what == "gemv_t" else rise.RISE_OP_N
+        ws = torch.empty(max(rise.rise_gemv_workspace(n, n, op), 1), device=dev,
+                         dtype=torch.uint8)
+        call = lambda i: rise.rise_gemv(y, A, x, n, n, lda=n, opA=op, ws=ws, stream=stream)
+    elif what == "iterate_sum":
+        x = torch.rand((1 << 26,), device=dev, generator=g) * 2 - 1
+        out = torch.empty(1, device=dev)
+        ws = torch.empty(max(rise.rise_iterate_sum_workspace(2, 1, 26), 1), device=dev,
+                         dtype=torch.uint8)
+        call = lambda i: rise.rise_iterate_sum(out, x, 2, 1, 26, ws=ws, stream=stream)
     else:  # batched
         plan, keep = batched_plan(rise, ri, torch, dev, "f32")
         call = lambda i: plan.launch(stream)
@@ -367,6 +383,29 @@ def gemv_leg(rise, torch, dev, stream):
         res[name] = {"us": round(ms * 1e3, 1), "gbps": round(gbs, 1),
                      "frac_hbm_peak": round(gbs / PEAK_HBM, 3)}
     del A
+    torch.cuda.empty_cache()
+    return res
+
+
+def iterate_leg(rise, torch, dev, stream):
+    """iterate with the tree-reduction body (binary tree, n = 2) over 2^26 FP32
+    values (256 MiB, read once) to one sum, and over 4096 rows of 2^14 values
+    to 4096 sums: HBM GB/s of the input read against the 8 TB/s peak."""
+    res = {}
+    for name, n, m, k in (("tree_2pow26_to_1", 2, 1, 26), ("rows_4096x2pow14", 2, 4096, 14)):
+        total = m * n ** k
+        g = torch.Generator(device=dev)
+        g.manual_seed(1300)
+        x = torch.rand((total,), device=dev, generator=g) * 2 - 1
+        out = torch.empty(m, device=dev)
+        need = rise.rise_iterate_sum_workspace(n, m, k)
+        ws = torch.empty(max(need, 1), device=dev, dtype=torch.uint8)
+        ms = event_ms(torch, stream, lambda: rise.rise_iterate_sum(out, x, n, m, k, ws=ws,
+                                                                   stream=stream), 20)
+        gbs = 4.0 * (total + m) / (ms * 1e-3) / 1e9
+        res[name] = {"us": round(ms * 1e3, 1), "gbps": round(gbs, 1),
+                     "frac_hbm_peak": round(gbs / PEAK_HBM, 3)}
+        del x
     torch.cuda.empty_cache()
     return res
 

@@ -131,6 +131,26 @@ size_t rise_gemv_workspace(int64_t M, int64_t K, rise_op opA);
 rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const float* x,
                       int64_t M, int64_t K, void* ws, size_t ws_bytes, void* stream);
 
+/* iterate (Sec. VI) with the tree-reduction body:
+ *   out = iterate(n, m, k, split(n) |> map(reduce(+, 0)), in)
+ * in: n^k * m floats (device), out: m floats (device).  Each of the k rounds
+ * replaces every group of n neighbouring values by their sum, a left fold from
+ * 0 in FP32 in index order; the rounds run in exactly that order, so out is
+ * bit-identical to a sequential float evaluation of the program (out[j] is the
+ * tree sum of in[j*n^k .. (j+1)*n^k)).  k = 0 copies m values; n = 1 adds 0 to
+ * every value (k rounds of it equal one); m = 0 is a no-op.
+ * Limits: 1 <= n <= 8192 (one group of a round is summed inside one
+ * workgroup), k >= 0, n^k * m < 2^40.
+ * Workspace: rise_iterate_sum_workspace(n, m, k) bytes, 256-byte aligned (the
+ * double buffer between kernel passes; 0 when one pass covers all rounds, and
+ * ws may then be NULL).
+ * Errors: NULL pointers, sizes outside the limits, out overlapping in, a
+ * short, misaligned or overlapping workspace return a status and enqueue
+ * nothing. */
+size_t rise_iterate_sum_workspace(int64_t n, int64_t m, int64_t k);
+rise_status rise_iterate_sum(float* out, const float* in, int64_t n, int64_t m, int64_t k,
+                             void* ws, size_t ws_bytes, void* stream);
+
 /* Gradients of L(C) with C = A . B (A: M x K, B: K x N, row-major FP32):
  *   dA = dC . transpose(B)   (M x K)     dB = transpose(A) . dC   (K x N)
  * written as two GEMMs that read transpose views of the stored operands (no

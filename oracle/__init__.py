@@ -60,6 +60,7 @@ def _load():
         "oracle_split3_bf16": [_P, _P, _P, _P, _I64],
         "oracle_quant_e4m3_blocks": [_P, _P, _P, _I64, _I64, _I64, _I64, _I64],
         "oracle_gemm_mode": [_P, _P, _P, _I64, _P, _I64, _P, _I64, _I64, _I64, _I64, _INT],
+        "oracle_iterate_sum": [_P, _P, _I64, _I64, _I64, _INT],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -204,6 +205,21 @@ def stencil2d_backward(dout, img, w, pad=PAD_CLAMP, want_din=True, want_dw=True)
     _check(lib.oracle_stencil2d_backward(_ptr(din), _ptr(dw), _ptr(dout), _ptr(img), _elem(img),
                                          W, H, W, _ptr(w), kh, kw, pad), "stencil2d_backward")
     return din, dw
+
+
+def iterate_sum(x, n, m, k, binary32=False):
+    """iterate(n, m, k, split(n) |> map(reduce(+, 0)), x) of Sec. VI: k rounds of
+    summing groups of n neighbours, n^k * m values in, m out.  binary32 rounds
+    every addition to float in the program's order; otherwise the sums are
+    doubles."""
+    lib = _load()
+    x = _c(np.asarray(x, dtype=np.float32)).reshape(-1)
+    if x.size != int(n) ** int(k) * int(m):
+        raise OracleError(f"iterate_sum: {x.size} values, expected n^k*m = {n}^{k}*{m}")
+    out = np.empty(int(m), dtype=np.float64)
+    _check(lib.oracle_iterate_sum(_ptr(out), _ptr(x), int(n), int(m), int(k), int(binary32)),
+           "iterate_sum")
+    return out
 
 
 def conv2d(x, w, pad=PAD_ZERO):

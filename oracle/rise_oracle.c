@@ -22,6 +22,9 @@
  *   - the 2D stencil is pad2D |> slide2D(k, 1) |> map(map(weighted reduce)).
  *   - gradients are the adjoints of these bilinear maps, written from their
  *     definitions (scatter through the same views; reduce over outputs).
+ *   - iterate (Sec. VI) with the tree-reduction body split(n) |> map(reduce(+, 0)):
+ *     k applications, each one turning an array of l*n values into l sums of n
+ *     neighbours, passed between two temporaries as newDoubleBuffer does.
  *   - operand preparation of the reduced-precision GEMM modes (bf16 rounding,
  *     hi/lo splitting, FP8 E4M3 with power-of-two block scales) written from
  *     the number formats' definitions in exact arithmetic.
@@ -932,4 +935,96 @@ int oracle_gemm_mode(double* C, const int64_t* rows, const int64_t* cols, int64_
     free(Bp[p]);
   }
   return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* iterate: the tree reduction of Sec. VI                                 */
+/* ---------------------------------------------------------------------- */
+
+/* iterate(n, m, k, body, arr) with body = split(n) |> map(reduce(+, 0)):
+ * arr holds n^k * m values; iteration i (0-based) reads the n^(k-i) * m values
+ * the previous one produced and writes n^(k-i-1) * m values, value j being the
+ * left fold from 0 of elements j*n .. j*n+n-1.  Two temporaries of n^k * m
+ * values take turns as the source and the destination (newDoubleBuffer); the
+ * first iteration reads arr and the last writes out.  k = 0 leaves arr as it is
+ * (out = arr).
+ *
+ * binary32 = 0: the values and every sum are doubles (exact widening of the
+ * float input).  binary32 = 1: the values and every sum are floats, so each
+ * addition rounds to binary32 in the order written here, the same order in
+ * which a float implementation of this program rounds. */
+static int64_t ipow_checked(int64_t n, int64_t k, int64_t m) {
+  /* n^k * m, or -1 when it exceeds 2^62 */
+  int64_t v = m;
+  for (int64_t i = 0; i < k; i++) {
+    if (n != 0 && v > ((int64_t)1 << 62) / n) return -1;
+    v *= n;
+  }
+  return v;
+}
+
+int oracle_iterate_sum(double* out, const float* in, int64_t n, int64_t m, int64_t k,
+                       int binary32) {
+  if (n < 1 || m < 0 || k < 0) return OR_ERR_ARG;
+  int64_t total = ipow_checked(n, k, m);
+  if (total < 0) return OR_ERR_SHAPE;
+  if (k == 0) {
+    for (int64_t j = 0; j < m; j++) out[j] = (double)in[j];
+    return OR_OK;
+  }
+  size_t cap = (size_t)(total > 0 ? total : 1);
+  if (binary32) {
+    float* buf[2] = {(float*)malloc(cap * sizeof(float)), (float*)malloc(cap * sizeof(float))};
+    if (!buf[0] || !buf[1]) {
+      free(buf[0]);
+      free(buf[1]);
+      return OR_ERR_ARG;
+    }
+    const float* src = in;
+    int64_t len = total;
+    for (int64_t i = 0; i < k; i++) {
+      int64_t l = len / n;
+      float* dst = buf[i & 1];
+      for (int64_t j = 0; j < l; j++) {
+        float acc = 0.0f;
+        for (int64_t t = 0; t < n; t++) acc = acc + src[j * n + t];
+        dst[j] = acc;
+      }
+      src = dst;
+      len = l;
+    }
+    for (int64_t j = 0; j < m; j++) out[j] = (double)src[j];
+    free(buf[0]);
+    free(buf[1]);
+    return OR_OK;
+  }
+  double* buf[2] = {(double*)malloc(cap * sizeof(double)), (double*)malloc(cap * sizeof(double))};
+  if (!buf[0] || !buf[1]) {
+    free(buf[0]);
+    free(buf[1]);
+    return OR_ERR_ARG;
+  }
+  int64_t len = total;
+  /* the first iteration reads the float input, later ones the temporaries */
+  for (int64_t j = 0; j < len / n; j++) {
+    double acc = 0.0;
+    for (int64_t t = 0; t < n; t++) acc = acc + (double)in[j * n + t];
+    buf[0][j] = acc;
+  }
+  len /= n;
+  for (int64_t i = 1; i < k; i++) {
+    int64_t l = len / n;
+    const double* src = buf[(i - 1) & 1];
+    double* dst = buf[i & 1];
+    for (int64_t j = 0; j < l; j++) {
+      double acc = 0.0;
+      for (int64_t t = 0; t < n; t++) acc = acc + src[j * n + t];
+      dst[j] = acc;
+    }
+    len = l;
+  }
+  for (int64_t j = 0; j < m; j++) out[j] = buf[(k - 1) & 1][j];
+  free(buf[0]);
+  free(buf[1]);
+  return OR_OK;
 }

@@ -109,6 +109,18 @@ def rise_gemv(y, A, x, M, K, *, lda, opA=RISE_OP_N, ws=None, stream=None):
     _check(st, "rise_gemv")
 
 
+def rise_iterate_sum_workspace(n, m, k):
+    return int(lib.rise_iterate_sum_workspace(n, m, k))
+
+
+def rise_iterate_sum(out, x, n, m, k, *, ws=None, stream=None):
+    """out (m floats) = iterate(n, m, k, split(n) |> map(reduce(+, 0)), x) (Sec. VI)."""
+    _require_cuda(out, x, ws)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    st = lib.rise_iterate_sum(_ptr(out), _ptr(x), n, m, k, _ptr(ws), ws_bytes, _stream(stream))
+    _check(st, "rise_iterate_sum")
+
+
 def rise_gemm_backward_workspace(M, N, K, mode):
     return int(lib.rise_gemm_backward_workspace(M, N, K, _mode(mode)))
 
@@ -308,6 +320,22 @@ def gemv(A, x, *, transA=False, out=None, stream=None):
     n = rise_gemv_workspace(M, K, op)
     ws = torch.empty(n, device=A.device, dtype=torch.uint8) if n else None
     rise_gemv(y, A, x, M, K, lda=A.stride(0), opA=op, ws=ws, stream=stream)
+    return y
+
+
+def iterate_sum(x, n, k, *, out=None, stream=None):
+    """Tree reduction of a float32 device tensor by iterate (Sec. VI): k rounds of
+    summing groups of n neighbours; x.numel() must be n^k * m, returns m values."""
+    _require_cuda(x)
+    x = x.contiguous().reshape(-1)
+    G = int(n) ** int(k)
+    if x.numel() % G:
+        raise ValueError(f"{x.numel()} values are not a multiple of n^k = {G}")
+    m = x.numel() // G
+    y = out if out is not None else torch.empty(m, device=x.device, dtype=torch.float32)
+    need = rise_iterate_sum_workspace(n, m, k)
+    ws = torch.empty(need, device=x.device, dtype=torch.uint8) if need else None
+    rise_iterate_sum(y, x, n, m, k, ws=ws, stream=stream)
     return y
 
 

@@ -261,6 +261,50 @@ rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const 
   return launch_gemv(a, ws, (hipStream_t)stream);
 }
 
+// n^k * m when it is below 2^40, else -1
+static int64_t iterate_len(int64_t n, int64_t m, int64_t k) {
+  const int64_t lim = (int64_t)1 << 40;
+  if (n < 1 || m < 0 || k < 0 || m >= lim) return -1;
+  if (n == 1) return m;
+  int64_t v = m;
+  for (int64_t i = 0; i < k && v > 0; i++) {
+    if (v > (lim - 1) / n) return -1;
+    v *= n;
+  }
+  return v;
+}
+
+size_t rise_iterate_sum_workspace(int64_t n, int64_t m, int64_t k) {
+  if (iterate_len(n, m, k) < 0 || n > iterate_max_fan_in() || m == 0) return 0;
+  return iterate_sum_workspace(n, m, k);
+}
+
+rise_status rise_iterate_sum(float* out, const float* in, int64_t n, int64_t m, int64_t k,
+                             void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (n < 1 || k < 0 || m < 0)
+    return fail(RISE_ERR_SHAPE, "rise_iterate_sum: needs n >= 1, m >= 0, k >= 0");
+  if (n > iterate_max_fan_in())
+    return fail(RISE_ERR_UNSUPPORTED, "rise_iterate_sum: fan-in n above 8192");
+  const int64_t len = iterate_len(n, m, k);
+  if (len < 0) return fail(RISE_ERR_SHAPE, "rise_iterate_sum: n^k * m must be below 2^40");
+  if (m == 0) return RISE_OK;
+  if (!out || !in) return fail(RISE_ERR_NULL, "rise_iterate_sum: out or in is NULL");
+  const Range ro = span(out, 1, m, m, 4), ri = span(in, 1, len, len, 4);
+  if (overlaps(ro, ri)) return fail(RISE_ERR_ALIAS, "rise_iterate_sum: out overlaps in");
+  const size_t need = iterate_sum_workspace(n, m, k);
+  if (need > 0) {
+    if (!ws || ws_bytes < need)
+      return fail(RISE_ERR_WORKSPACE, "rise_iterate_sum: workspace below rise_iterate_sum_workspace()");
+    if ((uintptr_t)ws & 255)
+      return fail(RISE_ERR_WORKSPACE, "rise_iterate_sum: workspace must be 256-byte aligned");
+    const Range rw{(uintptr_t)ws, (uintptr_t)ws + need};
+    if (overlaps(rw, ro) || overlaps(rw, ri))
+      return fail(RISE_ERR_ALIAS, "rise_iterate_sum: workspace overlaps out or in");
+  }
+  return launch_iterate_sum(out, in, n, m, k, ws, (hipStream_t)stream);
+}
+
 size_t rise_gemm_backward_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode) {
   size_t a = rise_gemm_workspace(M, K, N, mode, nullptr);  // dA: M x K, reduction over N
   size_t b = rise_gemm_workspace(K, N, M, mode, nullptr);  // dB: K x N, reduction over M

@@ -115,4 +115,12 @@ size_t gemv_workspace(int64_t M, int64_t K, bool trans);
 rise_status launch_gemv(const GemvArgs& a, void* ws, hipStream_t s);
 rise_status launch_stencil2d_backward(const StencilBwdArgs& a, void* ws, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// iterate with the tree-reduction body (iterate.hip)
+// ---------------------------------------------------------------------------
+int iterate_max_fan_in();
+size_t iterate_sum_workspace(int64_t n, int64_t m, int64_t k);
+rise_status launch_iterate_sum(float* out, const float* in, int64_t n, int64_t m, int64_t k,
+                               void* ws, hipStream_t s);
+
 }  // namespace rise

@@ -96,6 +96,31 @@ def test_gemv_rejections(lib):
     assert gemv(lib, M=0, y=None) == 0                  # no-op
 
 
+def iterate(lib, out=FAKE_C, x=FAKE_A, n=2, m=1, k=26, ws=None, ws_bytes=0):
+    return lib.rise_iterate_sum(out, x, n, m, k, ws, ws_bytes, None)
+
+
+def test_iterate_rejections(lib):
+    assert iterate(lib, out=None) == 1                   # NULL
+    assert iterate(lib, x=None) == 1
+    assert iterate(lib, n=0) == 2                        # SHAPE
+    assert iterate(lib, k=-1) == 2
+    assert iterate(lib, m=-3) == 2
+    assert iterate(lib, n=2, k=40) == 2                  # 2^40 values: above the limit
+    assert iterate(lib, n=8193, k=1) == 5                # UNSUPPORTED fan-in
+    assert iterate(lib, out=FAKE_A + 4096) == 3          # ALIAS: out inside in
+    # one pass (2^13 values fit one workgroup): no workspace; two passes: two halves
+    assert lib.rise_iterate_sum_workspace(2, 1, 13) == 0
+    need = lib.rise_iterate_sum_workspace(2, 1, 26)
+    assert need == 2 * 8192 * 4
+    assert iterate(lib) == 6                             # WORKSPACE missing
+    assert iterate(lib, ws=0x50000000, ws_bytes=need - 1) == 6
+    assert iterate(lib, ws=0x50000010, ws_bytes=need) == 6
+    assert iterate(lib, ws=FAKE_A, ws_bytes=need) == 3   # workspace inside in
+    assert iterate(lib, m=0, out=None, x=None) == 0      # no-op
+    assert lib.rise_iterate_sum_workspace(1, 5, 10 ** 12) == 0
+
+
 def test_gemm_degenerate_sizes_are_noops(lib):
     assert gemm(lib, M=0) == 0
     assert gemm(lib, N=0, C=None) == 0
