@@ -28,6 +28,7 @@ PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_BF16 = 2516.6       # TFLOP/s dense
 PEAK_FP8 = 5033.0
 PEAK_HBM = 8000.0        # GB/s
+PEAK_F32_VEC = 157.3     # TFLOP/s, MI355X FP32 vector (counts packed dual-issue FP32)
 
 M = N = K = 4096
 H = W = 4096
@@ -47,7 +48,8 @@ def parse():
                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     p.add_argument("--only", default=None,
                    choices=["gemm_f32", "gemm_bf16", "gemm_bf16x3", "gemm_fp8", "stencil",
-                            "conv_fwd", "conv_bwd", "batched", "gemv", "gemv_t", "iterate_sum"],
+                            "conv_fwd", "conv_bwd", "batched", "gemv", "gemv_t", "iterate_sum",
+                            "stencil_iterate", "stencil_iterate_1"],
                    help="run one kernel of the path --reps times (for profilers) and exit")
     p.add_argument("--reps", type=int, default=5)
     return p.parse_args()
@@ -192,6 +194,7 @@ def main():
         result["layer"] = layer_leg(rise, torch, dev, stream)
         result["gemv"] = gemv_leg(rise, torch, dev, stream)
         result["iterate_sum"] = iterate_leg(rise, torch, dev, stream)
+        result["stencil_iterate"] = stencil_iterate_leg(rise, ri, torch, dev, stream)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(ri, np, A, B, img, wts, value, ms_step)
     print(json.dumps(result), flush=True)
@@ -243,6 +246,16 @@ def run_only(what, reps, rise, ri, torch, dev, stream):
         ws = torch.empty(max(rise.rise_gemv_workspace(n, n, op), 1), device=dev,
                          dtype=torch.uint8)
         call = lambda i: rise.rise_gemv(y, A, x, n, n, lda=n, opA=op, ws=ws, stream=stream)
+    elif what in ("stencil_iterate", "stencil_iterate_1"):
+        img = torch.rand((H, W), device=dev, generator=g)
+        out = torch.empty_like(img)
+        w = torch.from_numpy(ri.gaussian_weights(KS, 1.0)).to(dev)
+        fuse = 1 if what.endswith("_1") else 4
+        ws = torch.empty(max(rise.rise_stencil2d_iterate_workspace(H, W, KS, KS, 16, fuse), 1),
+                         device=dev, dtype=torch.uint8)
+        call = lambda i: rise.rise_stencil2d_iterate(out, img, w, H, W, ld_out=W, ld_in=W, kh=KS,
+                                                     kw=KS, steps=16, fuse=fuse, ws=ws,
+                                                     stream=stream)
     elif what == "iterate_sum":
         x = torch.rand((1 << 26,), device=dev, generator=g) * 2 - 1
         out = torch.empty(1, device=dev)
@@ -384,6 +397,33 @@ def gemv_leg(rise, torch, dev, stream):
                      "frac_hbm_peak": round(gbs / PEAK_HBM, 3)}
     del A
     torch.cuda.empty_cache()
+    return res
+
+
+def stencil_iterate_leg(rise, ri, torch, dev, stream):
+    """16 steps of the 4096^2 5x5 Gaussian clamp stencil (iterate, Sec. VI): one
+    launch per step through the HBM double buffer, and 4 steps per launch in the
+    LDS double buffer.  Pixel-steps per second; the fused schedule against the
+    FP32 vector peak (k*k FMAs per pixel-step), the per-step one against HBM."""
+    steps = 16
+    img = torch.from_numpy(ri.image_uniform(H, W, 1003)).to(dev)
+    w = torch.from_numpy(ri.gaussian_weights(KS, 1.0)).to(dev)
+    out = torch.empty_like(img)
+    res = {}
+    for name, fuse in (("per_step", 1), ("fused4", 4)):
+        need = rise.rise_stencil2d_iterate_workspace(H, W, KS, KS, steps, fuse)
+        ws = torch.empty(max(need, 1), device=dev, dtype=torch.uint8)
+        ms = event_ms(torch, stream, lambda: rise.rise_stencil2d_iterate(
+            out, img, w, H, W, ld_out=W, ld_in=W, kh=KS, kw=KS, steps=steps, fuse=fuse, ws=ws,
+            stream=stream), 5)
+        pxs = H * W * steps / (ms * 1e-3)
+        res[name] = {"ms": round(ms, 3), "us_per_step": round(ms * 1e3 / steps, 1),
+                     "gpix_steps_per_s": round(pxs / 1e9, 1),
+                     "tflops": round(pxs * 2 * KS * KS / 1e12, 1),
+                     "hbm_gbps_equiv": round(pxs * 8 / 1e9, 1)}
+    res["fused4"]["frac_fp32_vector_peak"] = round(res["fused4"]["tflops"] / PEAK_F32_VEC, 3)
+    res["per_step"]["frac_hbm_peak"] = round(res["per_step"]["hbm_gbps_equiv"] / PEAK_HBM, 3)
+    res["speedup_fused"] = round(res["per_step"]["ms"] / res["fused4"]["ms"], 2)
     return res
 
 

@@ -227,6 +227,34 @@ rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t 
                            rise_pad pad, const rise_stencil_schedule* sched, void* stream);
 
 
+/* iterate (Sec. VI) with the stencil as a size-preserving body:
+ *   out = in |> stencil |> stencil |> ... (`steps` times)
+ * each application being rise_stencil2d(w, kh, kw, pad) of the previous image
+ * (steps = 0 copies in to out).  in, out: H x W FP32 (ld_in, ld_out), w as for
+ * rise_stencil2d; out must not overlap in.
+ * fuse selects the schedule, the number of steps one kernel launch runs:
+ *   1  one stencil launch per step through a double buffer of two H x W images
+ *      in the workspace (the paper's translation of iterate);
+ *   2 .. rise_stencil2d_iterate_max_fuse(): that many steps per launch, kept
+ *      in an LDS double buffer with a halo of fuse*(k-1)/2 (square 3x3 and
+ *      5x5 windows only; others return RISE_ERR_UNSUPPORTED);
+ *   0  the library default: 4 for 3x3 windows, 1 otherwise (for 5x5 the
+ *      fused steps are bound by the FMA rate and measured slower than one
+ *      HBM-bound launch per step).
+ * The last launch runs the remaining steps.  All schedules give identical
+ * results (each output is the same FP32 sum in the same order).
+ * Workspace: rise_stencil2d_iterate_workspace(H, W, kh, kw, steps, fuse) bytes,
+ * 256-byte aligned (0, one or two dense H x W images).  Errors as for
+ * rise_stencil2d, plus steps < 0, an unknown fuse, and a short, misaligned or
+ * overlapping workspace. */
+int32_t rise_stencil2d_iterate_max_fuse(void);
+size_t rise_stencil2d_iterate_workspace(int64_t H, int64_t W, int32_t kh, int32_t kw,
+                                        int64_t steps, int32_t fuse);
+rise_status rise_stencil2d_iterate(float* out, int64_t ld_out, const float* in, int64_t ld_in,
+                                   int64_t H, int64_t W, const float* w, int32_t kh, int32_t kw,
+                                   rise_pad pad, int64_t steps, int32_t fuse, void* ws,
+                                   size_t ws_bytes, void* stream);
+
 /* Gradients of L(out) with out = rise_stencil2d(in, w) (same sizes, window and
  * padding), given dOut (H x W):
  *   dIn = S^T dOut, the adjoint of pad2D |> slide2D |> weighted reduce: with

@@ -193,6 +193,21 @@ def stencil2d(img, w, pad=PAD_CLAMP):
     return out
 
 
+def stencil2d_iterate(img, w, steps, pad=PAD_CLAMP):
+    """iterate (Sec. VI) with the stencil as its size-preserving body: `steps`
+    applications, each to the image the previous one produced, held in two
+    float64 images that take turns (newDoubleBuffer); steps = 0 returns the
+    input."""
+    cur = np.asarray(img, dtype=np.float64)
+    if steps == 0:
+        return cur.copy()
+    bufs = [None, None]
+    for i in range(int(steps)):
+        bufs[i & 1] = stencil2d(cur, w, pad)
+        cur = bufs[i & 1]
+    return cur
+
+
 def stencil2d_backward(dout, img, w, pad=PAD_CLAMP, want_din=True, want_dw=True):
     lib = _load()
     img = _c(img)

@@ -174,6 +174,25 @@ def rise_stencil2d(out, inp, w, H, W, *, ld_out, ld_in, kh, kw, pad="clamp", sch
     _check(st, "rise_stencil2d")
 
 
+def rise_stencil2d_iterate_max_fuse():
+    return int(lib.rise_stencil2d_iterate_max_fuse())
+
+
+def rise_stencil2d_iterate_workspace(H, W, kh, kw, steps, fuse=0):
+    return int(lib.rise_stencil2d_iterate_workspace(H, W, kh, kw, steps, fuse))
+
+
+def rise_stencil2d_iterate(out, inp, w, H, W, *, ld_out, ld_in, kh, kw, steps, pad="clamp",
+                           fuse=0, ws=None, stream=None):
+    """`steps` applications of the stencil (iterate, Sec. VI); fuse = steps per launch."""
+    _require_cuda(out, inp, w, ws)
+    p = PADS[pad] if isinstance(pad, str) else int(pad)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    st = lib.rise_stencil2d_iterate(_ptr(out), ld_out, _ptr(inp), ld_in, H, W, _ptr(w), kh, kw, p,
+                                    steps, fuse, _ptr(ws), ws_bytes, _stream(stream))
+    _check(st, "rise_stencil2d_iterate")
+
+
 def rise_stencil2d_backward_workspace(H, W, kh, kw):
     return int(lib.rise_stencil2d_backward_workspace(H, W, kh, kw))
 
@@ -321,6 +340,22 @@ def gemv(A, x, *, transA=False, out=None, stream=None):
     ws = torch.empty(n, device=A.device, dtype=torch.uint8) if n else None
     rise_gemv(y, A, x, M, K, lda=A.stride(0), opA=op, ws=ws, stream=stream)
     return y
+
+
+def stencil2d_iterate(img, w, steps, pad="clamp", fuse=0, out=None, stream=None):
+    """`steps` applications of the 2D stencil to a float32 device image; allocates
+    the output and the double-buffer workspace with torch."""
+    img = img.contiguous()
+    w = w.contiguous().to(device=img.device, dtype=torch.float32)
+    H, W = img.shape
+    kh, kw = w.shape
+    if out is None:
+        out = torch.empty((H, W), device=img.device, dtype=torch.float32)
+    need = rise_stencil2d_iterate_workspace(H, W, kh, kw, steps, fuse)
+    ws = torch.empty(need, device=img.device, dtype=torch.uint8) if need else None
+    rise_stencil2d_iterate(out, img, w, H, W, ld_out=out.stride(0), ld_in=W, kh=kh, kw=kw,
+                           steps=steps, pad=pad, fuse=fuse, ws=ws, stream=stream)
+    return out
 
 
 def iterate_sum(x, n, k, *, out=None, stream=None):

@@ -54,6 +54,10 @@ _INT = ctypes.c_int
 SIGNATURES = {
     "rise_gemv_workspace": (_SZ, [_I64, _I64, _INT]),
     "rise_gemv": (_INT, [_P, _P, _I64, _INT, _P, _I64, _I64, _P, _SZ, _P]),
+    "rise_stencil2d_iterate_max_fuse": (_INT, []),
+    "rise_stencil2d_iterate_workspace": (_SZ, [_I64, _I64, _INT, _INT, _I64, _INT]),
+    "rise_stencil2d_iterate": (_INT, [_P, _I64, _P, _I64, _I64, _I64, _P, _INT, _INT, _INT, _I64,
+                                      _INT, _P, _SZ, _P]),
     "rise_iterate_sum_workspace": (_SZ, [_I64, _I64, _I64]),
     "rise_iterate_sum": (_INT, [_P, _P, _I64, _I64, _I64, _P, _SZ, _P]),
     "rise_status_string": (ctypes.c_char_p, [_INT]),

@@ -225,6 +225,64 @@ rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t 
   return launch_stencil2d(a, sc, (hipStream_t)stream);
 }
 
+int32_t rise_stencil2d_iterate_max_fuse(void) { return stencil_iterate_max_fuse(); }
+
+// the fuse a call runs with, or -1 when the request has no schedule
+static int iterate_fuse(int32_t kh, int32_t kw, int32_t fuse) {
+  if (fuse == 0) return stencil_iterate_default_fuse(kh, kw);
+  if (fuse == 1) return 1;
+  if (fuse < 0 || fuse > stencil_iterate_max_fuse() || !stencil_iterate_fusable(kh, kw))
+    return -1;
+  return fuse;
+}
+
+size_t rise_stencil2d_iterate_workspace(int64_t H, int64_t W, int32_t kh, int32_t kw,
+                                        int64_t steps, int32_t fuse) {
+  const int f = iterate_fuse(kh, kw, fuse);
+  if (!dim_ok(H) || !dim_ok(W) || steps < 0 || f < 0) return 0;
+  return stencil_iterate_workspace(H, W, steps, f);
+}
+
+rise_status rise_stencil2d_iterate(float* out, int64_t ld_out, const float* in, int64_t ld_in,
+                                   int64_t H, int64_t W, const float* w, int32_t kh, int32_t kw,
+                                   rise_pad pad, int64_t steps, int32_t fuse, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!dim_ok(H) || !dim_ok(W) || H * W >= kDimLimit * 2)
+    return fail(RISE_ERR_SHAPE, "rise_stencil2d_iterate: sizes must be in [0, 2^31)");
+  if (steps < 0 || steps >= kDimLimit)
+    return fail(RISE_ERR_SHAPE, "rise_stencil2d_iterate: steps must be in [0, 2^31)");
+  if (kh <= 0 || kw <= 0 || kh % 2 == 0 || kw % 2 == 0 || kh > 15 || kw > 15)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d_iterate: window sides must be odd and <= 15");
+  if (pad != RISE_PAD_CLAMP && pad != RISE_PAD_ZERO)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d_iterate: unknown pad mode");
+  const int f = iterate_fuse(kh, kw, fuse);
+  if (f < 0)
+    return fail(RISE_ERR_UNSUPPORTED,
+                "rise_stencil2d_iterate: fuse > 1 needs a square 3x3 or 5x5 window and at most "
+                "rise_stencil2d_iterate_max_fuse() steps");
+  if (H == 0 || W == 0) return RISE_OK;
+  if (!out || !in || !w) return fail(RISE_ERR_NULL, "rise_stencil2d_iterate: NULL pointer");
+  if (ld_in < W || ld_out < W) return fail(RISE_ERR_SHAPE, "rise_stencil2d_iterate: ld below W");
+  const Range ro = span(out, H, W, ld_out, 4), ri = span(in, H, W, ld_in, 4),
+              rw = span(w, kh, kw, kw, 4);
+  if (overlaps(ro, ri) || overlaps(ro, rw))
+    return fail(RISE_ERR_ALIAS, "rise_stencil2d_iterate: out overlaps in or w");
+  const size_t need = stencil_iterate_workspace(H, W, steps, f);
+  if (need > 0) {
+    if (!ws || ws_bytes < need)
+      return fail(RISE_ERR_WORKSPACE,
+                  "rise_stencil2d_iterate: workspace below rise_stencil2d_iterate_workspace()");
+    if ((uintptr_t)ws & 255)
+      return fail(RISE_ERR_WORKSPACE, "rise_stencil2d_iterate: workspace must be 256-byte aligned");
+    const Range rs{(uintptr_t)ws, (uintptr_t)ws + need};
+    if (overlaps(rs, ro) || overlaps(rs, ri) || overlaps(rs, rw))
+      return fail(RISE_ERR_ALIAS, "rise_stencil2d_iterate: workspace overlaps out, in or w");
+  }
+  StencilArgs a{out, ld_out, in, ld_in, (int)H, (int)W, w, kh, kw, (int)pad};
+  return launch_stencil_iterate(a, steps, f, ws, (hipStream_t)stream);
+}
+
 size_t rise_gemv_workspace(int64_t M, int64_t K, rise_op opA) {
   if (!dim_ok(M) || !dim_ok(K) || (opA != RISE_OP_N && opA != RISE_OP_T)) return 0;
   const size_t b = gemv_workspace(M, K, opA == RISE_OP_T);

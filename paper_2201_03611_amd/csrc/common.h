@@ -116,6 +116,16 @@ rise_status launch_gemv(const GemvArgs& a, void* ws, hipStream_t s);
 rise_status launch_stencil2d_backward(const StencilBwdArgs& a, void* ws, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// iterated stencil (stencil_iter.hip)
+// ---------------------------------------------------------------------------
+bool stencil_iterate_fusable(int kh, int kw);
+int stencil_iterate_max_fuse();
+int stencil_iterate_default_fuse(int kh, int kw);
+size_t stencil_iterate_workspace(int64_t H, int64_t W, int64_t steps, int fuse);
+rise_status launch_stencil_iterate(const StencilArgs& a, int64_t steps, int fuse, void* ws,
+                                   hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // iterate with the tree-reduction body (iterate.hip)
 // ---------------------------------------------------------------------------
 int iterate_max_fan_in();

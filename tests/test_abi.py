@@ -121,6 +121,40 @@ def test_iterate_rejections(lib):
     assert lib.rise_iterate_sum_workspace(1, 5, 10 ** 12) == 0
 
 
+def sit(lib, out=FAKE_C, ldo=64, x=FAKE_A, ldi=64, H=64, W=64, w=FAKE_W, kh=5, kw=5, pad=0,
+        steps=8, fuse=0, ws=None, ws_bytes=0):
+    return lib.rise_stencil2d_iterate(out, ldo, x, ldi, H, W, w, kh, kw, pad, steps, fuse, ws,
+                                      ws_bytes, None)
+
+
+def test_stencil_iterate_rejections(lib):
+    assert lib.rise_stencil2d_iterate_max_fuse() == 4
+    img = ((64 * 64 * 4 + 255) // 256) * 256
+    # default fuse 4 for 3x3: 8 steps are two launches, one workspace image;
+    # default 1 for 5x5: eight launches through both images
+    assert lib.rise_stencil2d_iterate_workspace(64, 64, 3, 3, 8, 0) == img
+    assert lib.rise_stencil2d_iterate_workspace(64, 64, 5, 5, 8, 0) == 2 * img
+    assert lib.rise_stencil2d_iterate_workspace(64, 64, 5, 5, 8, 4) == img
+    assert lib.rise_stencil2d_iterate_workspace(64, 64, 5, 5, 4, 4) == 0
+    assert lib.rise_stencil2d_iterate_workspace(64, 64, 7, 7, 2, 0) == img
+    assert sit(lib, out=None) == 1                        # NULL
+    assert sit(lib, w=None) == 1
+    assert sit(lib, steps=-1) == 2                        # SHAPE
+    assert sit(lib, ldi=63) == 2
+    assert sit(lib, kh=4) == 5                            # UNSUPPORTED
+    assert sit(lib, pad=7) == 5
+    assert sit(lib, fuse=5) == 5                          # above the largest fuse
+    assert sit(lib, fuse=-1) == 5
+    assert sit(lib, kh=7, kw=7, fuse=2) == 5              # fused 7x7 not offered
+    assert sit(lib, kh=3, kw=5, fuse=2) == 5
+    assert sit(lib, out=FAKE_A + 256) == 3                # ALIAS
+    assert sit(lib, fuse=4) == 6                          # WORKSPACE missing
+    assert sit(lib, fuse=4, ws=0x50000000, ws_bytes=img - 1) == 6
+    assert sit(lib, fuse=4, ws=0x50000010, ws_bytes=img) == 6
+    assert sit(lib, fuse=4, ws=FAKE_A, ws_bytes=img) == 3
+    assert sit(lib, H=0, out=None, x=None) == 0           # no-op
+
+
 def test_gemm_degenerate_sizes_are_noops(lib):
     assert gemm(lib, M=0) == 0
     assert gemm(lib, N=0, C=None) == 0
