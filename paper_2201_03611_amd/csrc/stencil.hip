@@ -73,14 +73,15 @@ __global__ __launch_bounds__(kThreads) void stencil2d_pipe(
   tiles::stencil_weights<K>(wt, w);
   tiles::StencilRegs<K, TY> st;
   uint32_t mode = 0;
+  const bool whole_chunks = VEC && (W & 3) == 0;  // the branch-free fetch needs W % 4 == 0
   auto fetch = [&](int y0, int x0) {
-    if (VEC)
+    if (whole_chunks)
       tiles::stencil_fetch_aligned<K, TY>(st, mode, in, ld_in, H, W, zero_pad, y0, x0);
     else
       tiles::stencil_fetch<K, VEC, TY>(st, in, ld_in, H, W, zero_pad, y0, x0);
   };
   auto stash = [&](f32x4* dst) {
-    if (VEC)
+    if (whole_chunks)
       tiles::stencil_stash_aligned<K, TY>(st, mode, dst);
     else
       tiles::stencil_stash<K, TY>(st, dst);

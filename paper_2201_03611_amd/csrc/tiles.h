@@ -412,9 +412,9 @@ __device__ __forceinline__ void stencil_stash(const StencilRegs<K, TY>& st,
   }
 }
 
-// Aligned rows (VEC): every 16-byte chunk of the halo tile is either wholly
-// inside or wholly outside the image (columns are multiples of 4 and W % 4 ==
-// 0), so the fetch can be branch-free: each chunk is loaded from a clamped,
+// Aligned rows (VEC and W % 4 == 0, which the callers check): every 16-byte
+// chunk of the halo tile is either wholly inside or wholly outside the image
+// (its columns start at a multiple of 4), so the fetch can be branch-free: each chunk is loaded from a clamped,
 // always valid address, and a 2-bit mode per chunk says what pad2D makes of
 // it (0 as loaded, 1 zero, 2 the first element repeated, 3 the last element
 // repeated); the mode is applied when the chunk is written to LDS, so the
@@ -549,7 +549,7 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
                                                  int H, int W, const float* __restrict__ w,
                                                  int zero_pad, int y0, int x0, f32x4* lds) {
   StencilRegs<K, TY> st;
-  if (VEC) {
+  if (VEC && (W & 3) == 0) {
     uint32_t mode;
     stencil_fetch_aligned<K, TY>(st, mode, in, ld_in, H, W, zero_pad, y0, x0);
     stencil_stash_aligned<K, TY>(st, mode, lds);

@@ -214,3 +214,32 @@ def test_autotune_table(rise):
     for p in gemms:
         check_gemm(p, host(p["dC"]))
     plan.destroy()
+
+
+def test_stencils_with_aligned_rows_and_ragged_width(rise):
+    # row pitch a multiple of 4 floats, width not: the last 16-byte chunk of a
+    # row straddles the edge, which the whole-chunk fetch must not be used for
+    import torch
+
+    g = ri.rng(31)
+    specs = [(50, 121, 124, 5, 0), (37, 258, 260, 3, 1), (70, 1021, 1024, 7, 0), (33, 6, 8, 5, 1)]
+    sp = (rise.RiseStencilProblem * len(specs))()
+    keep, refs = [], []
+    for i, (H, W, ld, k, pad) in enumerate(specs):
+        big = ri.uniform_matrix(g, H, ld, 0.0, 1.0)
+        img = np.ascontiguousarray(big[:, :W])
+        w = ri.random_weights(g, k)
+        din, dw = dev(big), dev(w)
+        out = torch.full((H, ld), float("nan"), device="cuda")
+        keep += [din, dw, out]
+        sp[i] = rise.RiseStencilProblem(out.data_ptr(), din.data_ptr(), dw.data_ptr(), H, W, ld, ld,
+                                        k, pad)
+        refs.append((img, w, pad, out, W))
+    print(f"batched stencils, aligned rows with ragged widths: {specs}", flush=True)
+    rise.rise_stencil2d_batched(sp, len(specs))
+    torch.cuda.synchronize()
+    for img, w, pad, out, W in refs:
+        p = oracle.PAD_ZERO if pad == 1 else oracle.PAD_CLAMP
+        o = host(out)
+        assert np.all(np.isnan(o[:, W:]))
+        assert componentwise(o[:, :W], oracle.stencil2d(img, w, p), stencil_scale(img, w, p)) <= TOL

@@ -105,6 +105,30 @@ def test_unaligned_leading_dimension(rise):
         assert componentwise(host(out)[:, :W], ref, stencil_scale(img, w, 0)) <= TOL_F32, sc
 
 
+@pytest.mark.parametrize("pad", list(PADS))
+@pytest.mark.parametrize("H,W,ld", [(50, 121, 124), (37, 258, 260), (300, 1022, 1024)])
+def test_aligned_rows_with_ragged_width(rise, pad, H, W, ld):
+    # 16-byte aligned rows (ld % 4 == 0) whose width is not a multiple of 4: the
+    # last 16-byte chunk of a row straddles the image edge, so the kernels must
+    # not take the whole-chunk fetch path
+    import torch
+
+    g = ri.rng(H + W + ld)
+    big = ri.uniform_matrix(g, H, ld, 0.0, 1.0)
+    img = np.ascontiguousarray(big[:, :W])
+    w = ri.uniform_matrix(g, 5, 5)
+    ref = oracle.stencil2d(img, w, PADS[pad])
+    scale = stencil_scale(img, w, PADS[pad])
+    for sc in rise.rise_stencil_schedules():
+        out = torch.full((H, ld), float("nan"), device="cuda")
+        print(f"stencil aligned ragged H={H} W={W} ld={ld} pad={pad} schedule={sc}", flush=True)
+        rise.rise_stencil2d(out, dev(big), dev(w), H, W, ld_out=ld, ld_in=ld, kh=5, kw=5,
+                            pad=pad, schedule=sc)
+        o = host(out)
+        assert np.all(np.isnan(o[:, W:])), sc
+        assert componentwise(o[:, :W], ref, scale) <= TOL_F32, sc
+
+
 def test_config_4096_gaussian_full(rise):
     # the timed stencil workload: 4096 x 4096 U[0,1), 5 x 5 Gaussian sigma = 1, clamp
     img = ri.image_uniform(4096, 4096, ri.SEED_STENCIL)
