@@ -183,7 +183,7 @@ def main():
                      "ms": round(t_gemm, 4)},
         "roofline_stencil": {"bound": "hbm", "achieved": round(sten_gbs, 1), "peak": PEAK_HBM,
                              "unit": "GB/s", "frac": round(sten_gbs / PEAK_HBM, 4),
-                             "traffic": sten_traffic, "kernel": "stencil2d_tiled<5,16 rows>",
+                             "traffic": sten_traffic, "kernel": "stencil2d_tiled<5,8 rows>",
                              "ms": round(t_sten, 5)},
     }
 

@@ -307,9 +307,11 @@ rise_status launch_stream(const StencilArgs& a, hipStream_t s) {
 template <int K, bool VEC>
 rise_status launch_k(const StencilArgs& a, const rise_stencil_schedule& sc, hipStream_t s) {
   if (sc.variant == RISE_STENCIL_LDS_TILE) {
+    if (sc.rows == 8) return launch_tiled<K, VEC, 8>(a, s);
     if (sc.rows == 16) return launch_tiled<K, VEC, 16>(a, s);
     if (sc.rows == 32) return launch_tiled<K, VEC, 32>(a, s);
   } else if (sc.variant == RISE_STENCIL_LDS_PIPE) {
+    if (sc.rows == 8) return launch_pipe<K, VEC, 8>(a, s);
     if (sc.rows == 16) return launch_pipe<K, VEC, 16>(a, s);
     if (sc.rows == 32) return launch_pipe<K, VEC, 32>(a, s);
   } else {
@@ -322,9 +324,10 @@ rise_status launch_k(const StencilArgs& a, const rise_stencil_schedule& sc, hipS
 }
 
 const rise_stencil_schedule kSchedules[] = {
-    {RISE_STENCIL_LDS_TILE, 16}, {RISE_STENCIL_LDS_TILE, 32}, {RISE_STENCIL_STREAM, 16},
-    {RISE_STENCIL_STREAM, 32},   {RISE_STENCIL_STREAM, 64},   {RISE_STENCIL_STREAM, 128},
-    {RISE_STENCIL_LDS_PIPE, 16}, {RISE_STENCIL_LDS_PIPE, 32}};
+    {RISE_STENCIL_LDS_TILE, 8},  {RISE_STENCIL_LDS_TILE, 16}, {RISE_STENCIL_LDS_TILE, 32},
+    {RISE_STENCIL_STREAM, 16},   {RISE_STENCIL_STREAM, 32},   {RISE_STENCIL_STREAM, 64},
+    {RISE_STENCIL_STREAM, 128},  {RISE_STENCIL_LDS_PIPE, 8},  {RISE_STENCIL_LDS_PIPE, 16},
+    {RISE_STENCIL_LDS_PIPE, 32}};
 
 }  // namespace
 
@@ -341,8 +344,9 @@ bool stencil_schedule_supported(const rise_stencil_schedule& sc) {
 }
 
 rise_stencil_schedule stencil_default_schedule(int H, int W, int kh, int kw) {
-  // measured on 4096^2: the 16-row LDS tile is fastest for 3x3, 5x5 and 7x7
-  return rise_stencil_schedule{RISE_STENCIL_LDS_TILE, 16};
+  // measured on 4096^2: the 8-row LDS tile (64 VGPRs, eight waves per SIMD) is
+  // fastest for 3x3 and 5x5, the 16-row tile for 7x7
+  return rise_stencil_schedule{RISE_STENCIL_LDS_TILE, kh <= 5 && kw <= 5 ? 8 : 16};
 }
 
 rise_status launch_stencil2d(const StencilArgs& a, const rise_stencil_schedule& sc,
