@@ -198,11 +198,16 @@ rise_status rise_prep_operand(void* out, int64_t rows_out, int64_t k_out, const 
  *    walks a fixed list of tiles and fetches tile i+1 into registers while it
  *    reduces tile i from a double-buffered LDS tile, so HBM traffic and the
  *    k*k FMAs overlap inside every workgroup.
+ *  RISE_STENCIL_ASYNC: the LDS halo tile filled by asynchronous global -> LDS
+ *    copies two tiles ahead through a ring of three LDS tiles (no registers
+ *    hold data in flight), on a resident grid; for 16-byte aligned rows with
+ *    W % 4 == 0 (other images run RISE_STENCIL_LDS_TILE with 16 rows).
  * rise_stencil_schedules() lists the supported (variant, rows) pairs. */
 typedef enum {
   RISE_STENCIL_LDS_TILE = 0,
   RISE_STENCIL_STREAM = 1,
-  RISE_STENCIL_LDS_PIPE = 2
+  RISE_STENCIL_LDS_PIPE = 2,
+  RISE_STENCIL_ASYNC = 3
 } rise_stencil_variant;
 typedef struct {
   int32_t variant; /* rise_stencil_variant */

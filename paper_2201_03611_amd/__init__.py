@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import (RISE_BF16, RISE_F32, RISE_MODE_BF16, RISE_MODE_BF16X3, RISE_MODE_BF16X6,
                    RISE_MODE_F32, RISE_MODE_FP8, RISE_OP_N, RISE_OP_T, RISE_PAD_CLAMP,
-                   RISE_PAD_ZERO, RISE_STENCIL_LDS_PIPE, RISE_STENCIL_LDS_TILE, RISE_STENCIL_STREAM,
+                   RISE_PAD_ZERO, RISE_STENCIL_ASYNC, RISE_STENCIL_LDS_PIPE, RISE_STENCIL_LDS_TILE,
+                   RISE_STENCIL_STREAM,
                    RiseGemmProblem,
                    RiseStencilProblem, RiseStencilSchedule, RiseTile)
 
@@ -147,7 +148,7 @@ def rise_prep_operand(out, rows_out, k_out, src, rows, K, ld_r, ld_k, mode, stre
 
 
 SCHEDULES = {"lds": RISE_STENCIL_LDS_TILE, "stream": RISE_STENCIL_STREAM,
-             "lds_pipe": RISE_STENCIL_LDS_PIPE}
+             "lds_pipe": RISE_STENCIL_LDS_PIPE, "async": RISE_STENCIL_ASYNC}
 
 
 def rise_stencil_schedules():

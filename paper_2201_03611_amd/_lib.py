@@ -20,7 +20,7 @@ RISE_OP_N, RISE_OP_T = 0, 1
 RISE_PAD_CLAMP, RISE_PAD_ZERO = 0, 1
 
 
-RISE_STENCIL_LDS_TILE, RISE_STENCIL_STREAM, RISE_STENCIL_LDS_PIPE = 0, 1, 2
+RISE_STENCIL_LDS_TILE, RISE_STENCIL_STREAM, RISE_STENCIL_LDS_PIPE, RISE_STENCIL_ASYNC = 0, 1, 2, 3
 
 
 class RiseTile(ctypes.Structure):

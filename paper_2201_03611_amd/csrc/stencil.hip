@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <climits>
 
 #include "common.h"
 #include "tiles.h"
@@ -105,6 +106,130 @@ __global__ __launch_bounds__(kThreads) void stencil2d_pipe(
     y0 = ny0;
     x0 = nx0;
     buf ^= 1;
+  }
+}
+
+// Asynchronous-copy schedule (aligned rows, W % 4 == 0): the halo tile goes
+// from HBM to LDS with global_load_lds (16 bytes per lane, no registers held),
+// DIST tiles ahead through a ring of DIST + 1 LDS tiles, so each workgroup
+// keeps DIST tiles of loads in flight while it reduces the current one.  pad2D
+// is applied in the copy addresses: rows through clamped row addresses (clamp)
+// or a page of zeros (zero); columns left or right of the image through the
+// zero page (zero) or, for clamp, by replacing those 16-byte chunks with the
+// edge element in registers when the window is read.  Every tile issues the same number of
+// copies and stores (outputs outside the image go to a dump page), so the
+// waits are fixed vmcnt counts.
+__device__ __align__(16) float g_stencil_zero_page[4];  // never written: zeros
+__device__ __align__(16) float g_stencil_dump_page[4];  // sink of out-of-image stores
+
+__device__ __forceinline__ void st_copy16_to_lds(const void* src, void* lds_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
+#endif
+}
+template <int N>
+__device__ __forceinline__ void st_wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt field is 6 bits");
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+#endif
+}
+__device__ __forceinline__ void st_wait_lgkmcnt0() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#endif
+}
+__device__ __forceinline__ void st_raw_barrier() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_barrier" ::: "memory");
+#endif
+}
+
+template <int K, int TY, int DIST>
+struct AsyncCfg {
+  static constexpr int R = (K - 1) / 2;
+  static constexpr int ROWS = TY + 2 * R;
+  static constexpr int CHUNKS = ROWS * tiles::kLChunks;  // 16-byte chunks of the halo tile
+  static constexpr int NI = (CHUNKS + 63) / 64;           // wave copy instructions per tile
+  static constexpr int QPW = (NI + 3) / 4;                // per wave (the last wave may have one less)
+  static constexpr int NST = TY / 4;                      // 16-byte stores per lane per tile
+  static constexpr int NBUF = DIST + 1;
+  static constexpr int STAGE = NI * 64;                   // chunks per LDS tile (rounded up)
+};
+
+template <int K, int TY, int DIST>
+__global__ __launch_bounds__(kThreads) void stencil2d_async(
+    float* __restrict__ out, int64_t ld_out, const float* __restrict__ in, int64_t ld_in, int H,
+    int W, const float* __restrict__ w, int zero_pad, int tiles_x, int ntiles, int per) {
+  using C = AsyncCfg<K, TY, DIST>;
+  constexpr int R = C::R, LC = tiles::kLChunks;
+  __shared__ f32x4 halo[C::NBUF][C::STAGE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int xcd = blockIdx.x % kNumXcd, j = blockIdx.x / kNumXcd;
+  const int band_end = (int)((int64_t)ntiles * (xcd + 1) / kNumXcd);
+  int t = (int)((int64_t)ntiles * xcd / kNumXcd) + j;
+  if (t >= band_end) return;  // the whole workgroup leaves before any barrier
+  const int last = band_end - 1;
+
+  float wt[K][K];
+  tiles::stencil_weights<K>(wt, w);
+
+  auto issue = [&](int tile, int buf) {
+    const int y0 = (tile / tiles_x) * TY, x0 = (tile % tiles_x) * TX;
+#pragma unroll
+    for (int q = 0; q < C::QPW; q++) {
+      const int g = wave + 4 * q;
+      if (g < C::NI) {
+        const int c = g * 64 + lane;
+        const void* src = g_stencil_zero_page;
+        if (c < C::CHUNKS) {
+          const int lr = c / LC, cc = c - lr * LC;
+          const int gy = y0 - R + lr, gx = x0 - tiles::kHalo + 4 * cc;
+          const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+          if (inside || !zero_pad)
+            src = in + (int64_t)clampi(gy, 0, H - 1) * ld_in + clampi(gx, 0, W - 4);
+        }
+        st_copy16_to_lds(src, &halo[buf][g * 64]);
+      }
+    }
+  };
+  const bool full_copies = wave + 4 * (C::QPW - 1) < C::NI;  // wave-uniform copy count
+
+#pragma unroll
+  for (int d = 0; d < DIST; d++) issue(min(t + d * per, last), d);
+  st_wait_vmcnt<0>();
+  int buf = 0;
+  while (true) {
+    const int next = t + per;
+    const bool more = next < band_end;
+    const int y0 = (t / tiles_x) * TY, x0 = (t % tiles_x) * TX;
+    st_wait_lgkmcnt0();  // this wave's reads of the previous tile are done
+    st_raw_barrier();    // every wave's copies into halo[buf] are visible
+    // refill the tile reduced in the previous iteration, DIST tiles ahead
+    issue(min(t + DIST * per, last), (buf + DIST) % C::NBUF);
+    // clamp at the left and right image edges: those chunks were copied from
+    // an arbitrary in-image address and are replaced in registers
+    const int x = x0 + 4 * lane;
+    const bool left = !zero_pad && x0 == 0;
+    const int lim = !zero_pad && x0 + TX + tiles::kHalo > W ? W : INT_MAX;
+    float res[TY / 4][4];
+    tiles::stencil_compute<K, TY, true>(res, wt, halo[buf], left, lim, x);
+    // the next tile's copies have landed: younger than them are the copies of
+    // DIST - 1 later tiles and the stores of DIST - 1 earlier tiles
+    if (full_copies)
+      st_wait_vmcnt<(DIST - 1) * (C::QPW + C::NST)>();
+    else
+      st_wait_vmcnt<(DIST - 1) * (C::QPW - 1 + C::NST)>();
+#pragma unroll
+    for (int o = 0; o < TY / 4; o++) {
+      const int y = y0 + wave * (TY / 4) + o;
+      float* dst = (y < H && x < W) ? out + (int64_t)y * ld_out + x : g_stencil_dump_page;
+      __builtin_nontemporal_store(f32x4{res[o][0], res[o][1], res[o][2], res[o][3]},
+                                  reinterpret_cast<f32x4*>(dst));
+    }
+    if (!more) break;
+    t = next;
+    buf = (buf + 1) % C::NBUF;
   }
 }
 
@@ -294,6 +419,29 @@ rise_status launch_pipe(const StencilArgs& a, hipStream_t s) {
   return check_launch("stencil2d_pipe");
 }
 
+template <int K, int TY>
+rise_status launch_async(const StencilArgs& a, hipStream_t s) {
+  constexpr int DIST = 2;
+  const int tiles_x = (a.W + TX - 1) / TX, tiles_y = (a.H + TY - 1) / TY;
+  const int64_t ntiles = (int64_t)tiles_x * tiles_y;
+  if (ntiles > INT32_MAX) return fail(RISE_ERR_SHAPE, "rise_stencil2d: too many tiles");
+  static const int occ = [] {
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, stencil2d_async<K, TY, DIST>, kThreads,
+                                                     0) != hipSuccess || o < 1)
+      o = 1;
+    return o;
+  }();
+  const int64_t band = (ntiles + kNumXcd - 1) / kNumXcd;
+  const int64_t max_per = std::max<int64_t>(1, (int64_t)occ * device_cu_count() / kNumXcd);
+  const int64_t rounds = (band + max_per - 1) / max_per;
+  const int per = (int)std::max<int64_t>(1, (band + rounds - 1) / rounds);
+  hipLaunchKernelGGL((stencil2d_async<K, TY, DIST>), dim3(kNumXcd * per), dim3(kThreads), 0, s,
+                     a.out, a.ld_out, a.in, a.ld_in, a.H, a.W, a.w, (int)(a.pad == RISE_PAD_ZERO),
+                     tiles_x, (int)ntiles, per);
+  return check_launch("stencil2d_async");
+}
+
 template <int K, bool VEC, int L>
 rise_status launch_stream(const StencilArgs& a, hipStream_t s) {
   int strips = (a.W + TX - 1) / TX, segs = (a.H + L - 1) / L;
@@ -314,6 +462,11 @@ rise_status launch_k(const StencilArgs& a, const rise_stencil_schedule& sc, hipS
     if (sc.rows == 8) return launch_pipe<K, VEC, 8>(a, s);
     if (sc.rows == 16) return launch_pipe<K, VEC, 16>(a, s);
     if (sc.rows == 32) return launch_pipe<K, VEC, 32>(a, s);
+  } else if (sc.variant == RISE_STENCIL_ASYNC) {
+    // whole 16-byte chunks only; other images take the LDS tile of the same rows
+    if (!VEC || (a.W & 3) != 0) return launch_tiled<K, VEC, 16>(a, s);
+    if (sc.rows == 8) return launch_async<K, 8>(a, s);
+    if (sc.rows == 16) return launch_async<K, 16>(a, s);
   } else {
     if (sc.rows == 16) return launch_stream<K, VEC, 16>(a, s);
     if (sc.rows == 32) return launch_stream<K, VEC, 32>(a, s);
@@ -327,7 +480,7 @@ const rise_stencil_schedule kSchedules[] = {
     {RISE_STENCIL_LDS_TILE, 8},  {RISE_STENCIL_LDS_TILE, 16}, {RISE_STENCIL_LDS_TILE, 32},
     {RISE_STENCIL_STREAM, 16},   {RISE_STENCIL_STREAM, 32},   {RISE_STENCIL_STREAM, 64},
     {RISE_STENCIL_STREAM, 128},  {RISE_STENCIL_LDS_PIPE, 8},  {RISE_STENCIL_LDS_PIPE, 16},
-    {RISE_STENCIL_LDS_PIPE, 32}};
+    {RISE_STENCIL_LDS_PIPE, 32}, {RISE_STENCIL_ASYNC, 8},    {RISE_STENCIL_ASYNC, 16}};
 
 }  // namespace
 

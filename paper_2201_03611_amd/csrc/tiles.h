@@ -462,9 +462,14 @@ __device__ __forceinline__ void stencil_stash_aligned(const StencilRegs<K, TY>& 
 
 // LDS -> k*k weighted sums.  Wave v computes output rows [y0 + v*TY/4,
 // y0 + (v+1)*TY/4); lane l owns columns x0 + 4l .. x0 + 4l + 3.
-template <int K, int TY>
+// EDGES (clamp padding with whole 16-byte chunks): the chunk left of column 0
+// (lane 0 when `left`) and every chunk right of column lim - 1 (lim is the
+// image width on the right-edge tile) read as the edge element, whatever the
+// LDS tile holds there.
+template <int K, int TY, bool EDGES = false>
 __device__ __forceinline__ void stencil_compute(float (&res)[TY / 4][4], const float (&wt)[K][K],
-                                                const f32x4* lds) {
+                                                const f32x4* lds, bool left = false,
+                                                int lim = 0, int x = 0) {
   constexpr int R = (K - 1) / 2;
   constexpr int RW = TY / 4;  // output rows per wave
   auto tile = reinterpret_cast<const f32x4(*)[kLChunks]>(lds);
@@ -479,6 +484,10 @@ __device__ __forceinline__ void stencil_compute(float (&res)[TY / 4][4], const f
     if (R > 0) {
       f32x4 c0 = tile[r0 + j][lane];
       f32x4 c2 = tile[r0 + j][lane + 2];
+      if (EDGES) {
+        if (left && lane == 0) c0 = f32x4{c1.x, c1.x, c1.x, c1.x};
+        if (x + 4 >= lim) c2 = f32x4{c1.w, c1.w, c1.w, c1.w};
+      }
       win[j][0] = c0.x; win[j][1] = c0.y; win[j][2] = c0.z; win[j][3] = c0.w;
       win[j][8] = c2.x; win[j][9] = c2.y; win[j][10] = c2.z; win[j][11] = c2.w;
     }
