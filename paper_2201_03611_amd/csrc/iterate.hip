@@ -239,7 +239,7 @@ rise_status launch_iterate_sum(float* out, const float* in, int64_t n, int64_t m
                                void* ws, hipStream_t s) {
   Pass ps[kMaxPasses];
   const int np = plan(n, m, k, ps, kMaxPasses);
-  if (np < 1) return RISE_ERR_SHAPE;
+  if (np < 1) return fail(RISE_ERR_SHAPE, "rise_iterate_sum: no pass plan for these sizes");
   const size_t half = ((size_t)ps[0].len_out * 4 + 255) / 256 * 256;
   float* buf[2] = {(float*)ws, (float*)((char*)ws + half)};
   const float* src = in;

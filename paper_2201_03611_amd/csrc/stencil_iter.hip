@@ -232,7 +232,7 @@ rise_status launch_fused(const StencilArgs& a, int steps, hipStream_t s) {
   const int TW = kItW - 2 * ItCfg<K>::R * steps;
   const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + kItTH - 1) / kItTH;
   const int64_t ntiles = (int64_t)tiles_x * tiles_y;
-  if (ntiles > INT32_MAX) return RISE_ERR_SHAPE;
+  if (ntiles > INT32_MAX) return fail(RISE_ERR_SHAPE, "rise_stencil2d_iterate: too many tiles");
   static const int occ = [] {
     int o = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, stencil_iter_fused<K>, kThreads, 0) !=
@@ -276,9 +276,10 @@ size_t stencil_iterate_workspace(int64_t H, int64_t W, int64_t steps, int fuse) 
 rise_status launch_stencil_iterate(const StencilArgs& a, int64_t steps, int fuse, void* ws,
                                    hipStream_t s) {
   if (steps == 0) {
-    if (hipMemcpy2DAsync(a.out, a.ld_out * 4, a.in, a.ld_in * 4, (size_t)a.W * 4, a.H,
-                         hipMemcpyDeviceToDevice, s) != hipSuccess)
-      return RISE_ERR_HIP;
+    const hipError_t e = hipMemcpy2DAsync(a.out, a.ld_out * 4, a.in, a.ld_in * 4,
+                                          (size_t)a.W * 4, a.H, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess)
+      return fail(RISE_ERR_HIP, std::string("rise_stencil2d_iterate: copy: ") + hipGetErrorString(e));
     return RISE_OK;
   }
   const int L = launches(steps, fuse);
