@@ -76,6 +76,8 @@ def _load():
     lib.oracle_e4m3_block_exponent.restype = _INT
     lib.oracle_num_threads.restype = _INT
     lib.oracle_last_threads.restype = _INT
+    lib.oracle_set_threads.argtypes = [_INT]
+    lib.oracle_set_threads.restype = _INT
     _lib = lib
     return lib
 
@@ -109,6 +111,11 @@ def num_threads():
 
 def last_threads():
     return _load().oracle_last_threads()
+
+
+def set_threads(n):
+    """OpenMP threads for the following calls; returns the previous setting."""
+    return _load().oracle_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

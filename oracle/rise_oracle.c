@@ -315,6 +315,18 @@ int oracle_num_threads(void) {
 
 int oracle_last_threads(void) { return oracle_threads_used; }
 
+/* Threads for the following calls (n >= 1); returns the previous setting. */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  int prev = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return prev;
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 static void note_threads(void) {
 #ifdef _OPENMP
 #pragma omp parallel
