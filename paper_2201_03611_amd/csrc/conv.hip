@@ -293,188 +293,178 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
 // ---------------------------------------------------------------------------
 // dW: each workgroup accumulates dW^T restricted to its tiles.
 //   dWt[o][tap * CI + ci] = sum over pixels of dOut[px][o] * in[px shifted by tap][ci]
-// Tile: 2 rows x 64 pixels.  M = CO (lane rows), K = the tile's 128 pixels, 8
-// consecutive pixels of one row per lane.  The 9*CI columns are split by the
-// tap column dx over three workgroups per tile group: workgroup 3 b + dx holds
-// one copy of the input halo, shifted by dx, and owns the columns
-// n' = dy * CI + ci of its dx (N = 3*CI), which keeps its LDS at a size that
-// lets three workgroups share a CU.
+// Tile: 2 rows x 64 pixels.  M = CO (lane rows), N = 9*CI (lane columns),
+// K = the tile's 128 pixels, 8 consecutive pixels of one row per lane.
+// The tiles sit in LDS as stored (NHWC: a pixel's channels contiguous, rows
+// padded by 16 bytes) and the MFMA fragments, which need 8 consecutive pixels
+// of one channel per lane, are read with the gfx950 LDS transpose read
+// ds_read_b64_tr_b16.  Within each group of 16 lanes it takes the 16 addresses
+// as a 16 x 4 block of 16-bit values M[s][e] (lane s supplies the 4 values at
+// its address) and returns M[4 j + i / 4][i % 4] as element j of lane i.  With
+// source lane s = 4 j + q pointing at channels c0 + 4 q .. + 3 of pixel k0 + j,
+// lane i receives channel c0 + i at pixels k0 .. k0 + 3.  One copy of the
+// input halo then serves all three tap columns (a tap column is a shift of
+// the pixel address).
 // ---------------------------------------------------------------------------
 constexpr int WTY = 2;               // rows per dW tile
 constexpr int WHR = WTY + 2;         // halo rows
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+// 4 consecutive pixels of one channel per lane (see above); p points at the
+// 16-bit value this lane supplies as a source.
+__device__ __forceinline__ s16x4 read_tr16(const uint16_t* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)p);
+#else
+  return s16x4{0, 0, 0, 0};
+#endif
+}
 
 template <int CI, int CO>
 __global__ __launch_bounds__(kThreads) void conv3x3_dw(
     float* __restrict__ partial, const uint16_t* __restrict__ dout,
     const uint16_t* __restrict__ in, int B, int H, int W, int zero_pad, int tiles_x,
     int tiles_y, int ntiles) {
-  constexpr int NN = 3 * CI;                          // columns of one dx group
-  constexpr int NBLK = (CO / 32) * (NN / 32);         // 32 x 32 blocks of the group's dW^T
+  constexpr int NBLK = (CO / 32) * (TAPS * CI / 32);  // 32 x 32 blocks of dW^T
   constexpr int PER_WAVE = (NBLK + 3) / 4;            // wave w owns blocks w, w + 4, ...
   static_assert(CI % 32 == 0 && CO % 32 == 0, "channel counts");
+  static_assert(4 % (CO / 32) == 0, "a wave's blocks share one row block of dW^T");
   constexpr int PXT = WTY * TXP;                      // pixels per tile (128)
-  // dOut tile transposed: go[o * GP + p], p = r * TXP + x; input halo transposed and
-  // shifted by dx: xs[ci * XP + hr * TXP + p] = in[row hr][pixel p + dx - 1][ci].
-  // The per-channel strides GP and XP are odd multiples of 16 bytes, so the 32
-  // channels a half-wave reads fall in distinct bank groups.
-  constexpr int GP = PXT + 8;
-  constexpr int XP = WHR * TXP + 8;
-  __shared__ __attribute__((aligned(16))) uint16_t go[CO * GP];
-  __shared__ __attribute__((aligned(16))) uint16_t xs[CI * XP];
+  constexpr int GS = CO + 8;                          // dOut pixel stride (16-bit values)
+  constexpr int XS = CI + 8;                          // input pixel stride
+  __shared__ __attribute__((aligned(16))) uint16_t go[PXT * GS];       // [pixel][o]
+  __shared__ __attribute__((aligned(16))) uint16_t xs[WHR * HC * XS];  // [row][column][ci]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int il = lane & 31, kh = lane >> 5;
-  // Workgroup b runs on XCD b % 8.  The three workgroups of a tile group (one
-  // per dx) are b = xcd + 8 (3 k + dx), so they share an XCD and its L2 (they
-  // read the same dOut tile); a group walks a contiguous run of tiles, in which
-  // vertically neighbouring tiles (two shared halo rows) follow each other.
-  const int xcd = blockIdx.x % kNumXcd, jb = blockIdx.x / kNumXcd;
-  const int dx = jb % 3, grp = xcd + kNumXcd * (jb / 3), ngrp = gridDim.x / 3;
-  const int run = (ntiles + ngrp - 1) / ngrp;
-  const int t_end = min(ntiles, (grp + 1) * run);
+  // transpose-read source coordinates of this lane: pixel offset and channel offset
+  const int grp16 = lane >> 4, i16 = lane & 15;
+  const int src_px = 8 * (grp16 >> 1) + (i16 >> 2);   // + 4 for the second read
+  const int src_ch = 16 * (grp16 & 1) + 4 * (i16 & 3);
+  // Workgroup b runs on XCD b % 8; a workgroup walks a contiguous run of tiles,
+  // in which vertically neighbouring tiles (two shared halo rows) follow each other.
+  const int run = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int t0 = blockIdx.x * run, t_end = min(ntiles, t0 + run);
   f32x16 acc[PER_WAVE];
 #pragma unroll
   for (int q = 0; q < PER_WAVE; q++)
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[q][r] = 0.f;
 
-  for (int t = grp * run; t < t_end; t++) {
+  for (int t = t0; t < t_end; t++) {
     const int b = t / (tiles_x * tiles_y);
     const int rem = t - b * tiles_x * tiles_y;
     const int ty = rem % tiles_y, tx = rem / tiles_y;
     const int y0 = ty * WTY, x0 = tx * TXP;
     const uint16_t* img = in + (int64_t)b * H * W * CI;
     const uint16_t* g = dout + (int64_t)b * H * W * CO;
-    __syncthreads();
-    // All loads of a tile are issued before any of them is used (every address
-    // is clamped into the image, and a flag says which values padding zeroes),
-    // so their latencies overlap.
-    constexpr int NG = (PXT / 2) * (CO / 8) / kThreads;     // dOut items per thread
-    constexpr int NX = WHR * (TXP / 2) * (CI / 8) / kThreads;  // input items per thread
-    static_assert((PXT / 2) * (CO / 8) % kThreads == 0 && WHR * (TXP / 2) * (CI / 8) % kThreads == 0,
-                  "whole items per thread");
-    static_assert(2 * (NG + NX) <= 32, "zero-flag bits");
-    i32x4 gv[NG][2], xv[NX][2];
+    // All 16-byte loads of a tile are issued before any is used (clamped
+    // addresses; a flag says which values padding zeroes).
+    constexpr int NGC = PXT * (CO / 8);                 // dOut chunks
+    constexpr int NXC = WHR * HC * (CI / 8);            // input halo chunks
+    constexpr int NG = NGC / kThreads;
+    constexpr int NX = (NXC + kThreads - 1) / kThreads;
+    static_assert(NGC % kThreads == 0 && NG + NX <= 32, "chunks per thread");
+    i32x4 gv[NG], xv[NX];
     uint32_t zero = 0;
-    auto load_px = [&](const uint16_t* base, int C, int gy, int gx, int ch) {
-      const int gyc = gy < 0 ? 0 : (gy >= H ? H - 1 : gy), gxc = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
-      return reinterpret_cast<const i32x4*>(base + ((int64_t)gyc * W + gxc) * C)[ch];
-    };
 #pragma unroll
     for (int i = 0; i < NG; i++) {
-      // dOut tile -> go[o][p] (zero outside the image: those outputs do not exist)
-      const int c = tid + i * kThreads, j = c % (PXT / 2), ch = c / (PXT / 2);
-      const int p = 2 * j, gy = y0 + p / TXP, gx = x0 + p % TXP;
-#pragma unroll
-      for (int e = 0; e < 2; e++) {
-        gv[i][e] = load_px(g, CO, gy, gx + e, ch);
-        if (gy >= H || gx + e >= W) zero |= 1u << (2 * i + e);
-      }
+      const int c = tid + i * kThreads, p = c / (CO / 8), ch = c - p * (CO / 8);
+      const int gy = y0 + p / TXP, gx = x0 + p % TXP;
+      const int gyc = gy >= H ? H - 1 : gy, gxc = gx >= W ? W - 1 : gx;
+      gv[i] = reinterpret_cast<const i32x4*>(g + ((int64_t)gyc * W + gxc) * CO)[ch];
+      if (gy >= H || gx >= W) zero |= 1u << i;  // outputs outside the image do not exist
     }
 #pragma unroll
     for (int i = 0; i < NX; i++) {
-      // input halo row hr, shifted so that pixel p holds halo column p + dx
-      const int c = tid + i * kThreads, j = c % (TXP / 2), rest = c / (TXP / 2);
-      const int hr = rest % WHR, ch = rest / WHR;
-      const int p = 2 * j, gy = y0 - 1 + hr, gx = x0 - 1 + p + dx;
-#pragma unroll
-      for (int e = 0; e < 2; e++) {
-        xv[i][e] = load_px(img, CI, gy, gx + e, ch);
-        const bool inside = gy >= 0 && gy < H && gx + e >= 0 && gx + e < W;
-        if (zero_pad && !inside) zero |= 1u << (2 * (NG + i) + e);
-      }
+      const int c = min(tid + i * kThreads, NXC - 1), hp = c / (CI / 8), ch = c - hp * (CI / 8);
+      const int hr = hp / HC, hc = hp - hr * HC;
+      const int gy = y0 - 1 + hr, gx = x0 - 1 + hc;
+      const int gyc = gy < 0 ? 0 : (gy >= H ? H - 1 : gy), gxc = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
+      xv[i] = reinterpret_cast<const i32x4*>(img + ((int64_t)gyc * W + gxc) * CI)[ch];
+      const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      if (zero_pad && !inside) zero |= 1u << (NG + i);
     }
-    // Stores, channel-major (pixels contiguous per channel, the MFMA's K order):
-    // each item is a pair of neighbouring pixels and 8 channels, written as 8
-    // four-byte words (one per channel) holding the two pixels' values;
-    // consecutive lanes take consecutive pixel pairs, so every write covers 64
-    // consecutive words (no bank conflicts).
-    auto pack = [](const i32x4& a, const i32x4& b, int q) {
-      const uint32_t wa = (uint32_t)a[q >> 1], wb = (uint32_t)b[q >> 1];
-      return (q & 1) ? (wa >> 16) | (wb & 0xffff0000u) : (wa & 0xffffu) | (wb << 16);
-    };
+    __syncthreads();  // every wave is done reading the previous tile
     const i32x4 z4 = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < NG; i++) {
-      const int c = tid + i * kThreads, j = c % (PXT / 2), ch = c / (PXT / 2), p = 2 * j;
-      const i32x4 a = (zero >> (2 * i)) & 1u ? z4 : gv[i][0];
-      const i32x4 b = (zero >> (2 * i + 1)) & 1u ? z4 : gv[i][1];
-#pragma unroll
-      for (int q = 0; q < 8; q++)
-        *reinterpret_cast<uint32_t*>(&go[(ch * 8 + q) * GP + p]) = pack(a, b, q);
+      const int c = tid + i * kThreads, p = c / (CO / 8), ch = c - p * (CO / 8);
+      *reinterpret_cast<i32x4*>(&go[p * GS + 8 * ch]) = (zero >> i) & 1u ? z4 : gv[i];
     }
 #pragma unroll
     for (int i = 0; i < NX; i++) {
-      const int c = tid + i * kThreads, j = c % (TXP / 2), rest = c / (TXP / 2);
-      const int hr = rest % WHR, ch = rest / WHR, p = 2 * j;
-      const i32x4 a = (zero >> (2 * (NG + i))) & 1u ? z4 : xv[i][0];
-      const i32x4 b = (zero >> (2 * (NG + i) + 1)) & 1u ? z4 : xv[i][1];
-#pragma unroll
-      for (int q = 0; q < 8; q++)
-        *reinterpret_cast<uint32_t*>(&xs[(ch * 8 + q) * XP + hr * TXP + p]) = pack(a, b, q);
+      const int c = tid + i * kThreads;
+      if (c < NXC) {
+        const int hp = c / (CI / 8), ch = c - hp * (CI / 8);
+        *reinterpret_cast<i32x4*>(&xs[hp * XS + 8 * ch]) = (zero >> (NG + i)) & 1u ? z4 : xv[i];
+      }
     }
     __syncthreads();
-    // K loop over the tile's pixels: 8 per lane, rows r = 0..WTY-1, 64 pixels each
+    // K loop over the tile's pixels: 16 per step, rows r = 0..WTY-1, 64 pixels each
+    const int mb = wave % (CO / 32);  // the row block of dW^T all of this wave's blocks share
 #pragma unroll
     for (int ks = 0; ks < PXT / 16; ks++) {
       const int r = (16 * ks) / TXP;
-      const int p0 = (16 * ks) % TXP + 8 * kh;
+      const int pb = (16 * ks) % TXP + src_px;  // this lane's source pixel in row r
+      bf16x8 av;
+      {
+        const uint16_t* pa = &go[(r * TXP + pb) * GS + 32 * mb + src_ch];
+        const s16x4 lo = read_tr16(pa), hi = read_tr16(pa + 4 * GS);
+        av = __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+      }
 #pragma unroll
       for (int q = 0; q < PER_WAVE; q++) {
         const int blk = wave + 4 * q;
         if (blk >= NBLK) break;  // wave-uniform
-        const int mb = blk % (CO / 32), nb = blk / (CO / 32);
-        const int o = 32 * mb + il;
-        const int n = 32 * nb + il;  // n = dy * CI + ci
-        const int dy = n / CI, ci = n - dy * CI;
-        const bf16x8 av =
-            __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(&go[o * GP + r * TXP + p0]));
-        const bf16x8 bv = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const i32x4*>(&xs[ci * XP + (r + dy) * TXP + p0]));
+        const int nb = blk / (CO / 32);
+        const int n0 = 32 * nb;  // n = tap * CI + ci
+        const int tap = n0 / CI, c0 = n0 - tap * CI;
+        const int dy = tap / 3, dx = tap - dy * 3;
+        const uint16_t* pbv = &xs[((r + dy) * HC + pb + dx) * XS + c0 + src_ch];
+        const s16x4 lo = read_tr16(pbv), hi = read_tr16(pbv + 4 * XS);
+        const bf16x8 bv =
+            __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
         acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[q], 0, 0, 0);
       }
     }
   }
-  // partial[dx][group][o][dy * CI + ci] of dW^T
-  float* dst = partial + ((int64_t)dx * ngrp + grp) * CO * NN;
+  // partial[block][o][n] of dW^T
+  float* dst = partial + (int64_t)blockIdx.x * CO * TAPS * CI;
 #pragma unroll
   for (int q = 0; q < PER_WAVE; q++) {
     const int blk = wave + 4 * q;
     if (blk >= NBLK) break;
-    const int mb = blk % (CO / 32), nb = blk / (CO / 32);
+    const int mbq = blk % (CO / 32), nb = blk / (CO / 32);
 #pragma unroll
     for (int r = 0; r < 16; r++) {
-      const int o = 32 * mb + 8 * (r >> 2) + 4 * kh + (r & 3);
+      const int o = 32 * mbq + 8 * (r >> 2) + 4 * kh + (r & 3);
       const int n = 32 * nb + il;
-      dst[(int64_t)o * NN + n] = acc[q][r];
+      dst[(int64_t)o * TAPS * CI + n] = acc[q][r];
     }
   }
 }
 
-// dW[co][ci][tap] = sum over the groups of tap column dx = tap % 3 of
-// partial[dx][group][co][dy * CI + ci], dy = tap / 3 (fixed order)
+// dW[co][ci][tap] = sum over blocks of partial[block][co][tap * CI + ci] (fixed order)
 __global__ __launch_bounds__(kThreads) void conv_dw_reduce(float* __restrict__ dw,
                                                            const float* __restrict__ partial,
-                                                           int groups, int CO, int CI) {
+                                                           int blocks, int CO, int CI) {
   const int n = CO * TAPS * CI;
   const int e = blockIdx.x * kThreads + threadIdx.x;
   if (e >= n) return;
-  const int o = e / (TAPS * CI), rem = e - o * TAPS * CI, tap = rem / CI, ci = rem - tap * CI;
-  const int dy = tap / 3, dx = tap - 3 * dy;
-  const int64_t plane = (int64_t)CO * 3 * CI;
-  const float* src = partial + (int64_t)dx * groups * plane + (int64_t)o * 3 * CI + dy * CI + ci;
   float s = 0.f;
-  for (int q = 0; q < groups; q++) s += src[q * plane];
+  for (int q = 0; q < blocks; q++) s += partial[(int64_t)q * n + e];
+  const int o = e / (TAPS * CI), rem = e - o * TAPS * CI, tap = rem / CI, ci = rem - tap * CI;
   dw[((int64_t)o * CI + ci) * TAPS + tap] = s;
 }
 
-// Tile groups of the dW kernel (each is three workgroups, one per tap column);
-// a multiple of the 8 XCDs, groups past the last tile contribute zeros.
+// Persistent workgroups of the dW kernel (each walks a contiguous run of tiles).
 int dw_blocks(int B, int H, int W) {
   int64_t tiles = (int64_t)B * ((H + WTY - 1) / WTY) * ((W + TXP - 1) / TXP);
-  int64_t blocks = 256 * 2;  // 1536 workgroups: two rounds at three per CU on 256 CUs
-  if (tiles < blocks) blocks = (tiles + kNumXcd - 1) / kNumXcd * kNumXcd;
-  return (int)blocks;
+  int64_t blocks = 256 * 2;  // two workgroups per CU on 256 CUs
+  return (int)(tiles < blocks ? tiles : blocks);
 }
 
 template <int CI, int CO>
@@ -507,7 +497,7 @@ rise_status launch_dw(float* partial, const uint16_t* dout, const uint16_t* in, 
                       int W, int zero, hipStream_t s) {
   const int tiles_x = (W + TXP - 1) / TXP, tiles_y = (H + WTY - 1) / WTY;
   const int ntiles = B * tiles_x * tiles_y;
-  const int grid = 3 * dw_blocks(B, H, W);
+  const int grid = dw_blocks(B, H, W);
   hipLaunchKernelGGL((conv3x3_dw<CI, CO>), dim3(grid), dim3(kThreads), 0, s, partial, dout, in, B,
                      H, W, zero, tiles_x, tiles_y, ntiles);
   return check_launch("conv3x3_dw");
