@@ -353,22 +353,24 @@ __global__ __launch_bounds__(kThreads) void conv3x3_dw(
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[q][r] = 0.f;
 
-  for (int t = t0; t < t_end; t++) {
+  // All 16-byte loads of a tile are issued together (clamped addresses; a flag
+  // says which values padding zeroes), one tile ahead: they are in flight
+  // while the current tile's MFMAs run.
+  constexpr int NGC = PXT * (CO / 8);                 // dOut chunks
+  constexpr int NXC = WHR * HC * (CI / 8);            // input halo chunks
+  constexpr int NG = NGC / kThreads;
+  constexpr int NX = (NXC + kThreads - 1) / kThreads;
+  static_assert(NGC % kThreads == 0 && NG + NX <= 32, "chunks per thread");
+  i32x4 gv[NG], xv[NX];
+  uint32_t zero = 0;
+  auto fetch = [&](int t) {
     const int b = t / (tiles_x * tiles_y);
     const int rem = t - b * tiles_x * tiles_y;
     const int ty = rem % tiles_y, tx = rem / tiles_y;
     const int y0 = ty * WTY, x0 = tx * TXP;
     const uint16_t* img = in + (int64_t)b * H * W * CI;
     const uint16_t* g = dout + (int64_t)b * H * W * CO;
-    // All 16-byte loads of a tile are issued before any is used (clamped
-    // addresses; a flag says which values padding zeroes).
-    constexpr int NGC = PXT * (CO / 8);                 // dOut chunks
-    constexpr int NXC = WHR * HC * (CI / 8);            // input halo chunks
-    constexpr int NG = NGC / kThreads;
-    constexpr int NX = (NXC + kThreads - 1) / kThreads;
-    static_assert(NGC % kThreads == 0 && NG + NX <= 32, "chunks per thread");
-    i32x4 gv[NG], xv[NX];
-    uint32_t zero = 0;
+    zero = 0;
 #pragma unroll
     for (int i = 0; i < NG; i++) {
       const int c = tid + i * kThreads, p = c / (CO / 8), ch = c - p * (CO / 8);
@@ -387,6 +389,9 @@ __global__ __launch_bounds__(kThreads) void conv3x3_dw(
       const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
       if (zero_pad && !inside) zero |= 1u << (NG + i);
     }
+  };
+  if (t0 < t_end) fetch(t0);
+  for (int t = t0; t < t_end; t++) {
     __syncthreads();  // every wave is done reading the previous tile
     const i32x4 z4 = {0, 0, 0, 0};
 #pragma unroll
@@ -402,6 +407,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_dw(
         *reinterpret_cast<i32x4*>(&xs[hp * XS + 8 * ch]) = (zero >> (NG + i)) & 1u ? z4 : xv[i];
       }
     }
+    if (t + 1 < t_end) fetch(t + 1);
     __syncthreads();
     // K loop over the tile's pixels: 16 per step, rows r = 0..WTY-1, 64 pixels each
     const int mb = wave % (CO / 32);  // the row block of dW^T all of this wave's blocks share
