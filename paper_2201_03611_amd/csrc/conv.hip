@@ -460,8 +460,17 @@ __global__ __launch_bounds__(kThreads) void conv_dw_reduce(float* __restrict__ d
   const int n = CO * TAPS * CI;
   const int e = blockIdx.x * kThreads + threadIdx.x;
   if (e >= n) return;
+  // the sum runs in block order; the loads of 8 blocks are issued together
   float s = 0.f;
-  for (int q = 0; q < blocks; q++) s += partial[(int64_t)q * n + e];
+  int q = 0;
+  for (; q + 8 <= blocks; q += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = partial[(int64_t)(q + u) * n + e];
+#pragma unroll
+    for (int u = 0; u < 8; u++) s += v[u];
+  }
+  for (; q < blocks; q++) s += partial[(int64_t)q * n + e];
   const int o = e / (TAPS * CI), rem = e - o * TAPS * CI, tap = rem / CI, ci = rem - tap * CI;
   dw[((int64_t)o * CI + ci) * TAPS + tap] = s;
 }

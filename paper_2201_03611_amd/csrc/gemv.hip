@@ -154,8 +154,17 @@ __global__ void gemv_reduce(float* __restrict__ y, const float* __restrict__ par
                             int nparts) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
+  // fixed order (part 0 first); the loads of 8 parts are issued together
   float s = 0.f;
-  for (int p = 0; p < nparts; p++) s += part[(int64_t)p * M + m];  // fixed order
+  int p = 0;
+  for (; p + 8 <= nparts; p += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = part[(int64_t)(p + u) * M + m];
+#pragma unroll
+    for (int u = 0; u < 8; u++) s += v[u];
+  }
+  for (; p < nparts; p++) s += part[(int64_t)p * M + m];
   y[m] = s;
 }
 
