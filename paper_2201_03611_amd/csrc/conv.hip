@@ -40,6 +40,14 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float x) {
   return (uint16_t)(u >> 16);
 }
 
+// Two floats to two bf16 (round to nearest even) in one 32-bit word, low half
+// first: one v_cvt_pk_bf16_f32 on gfx950.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
+}
+
 // dst[o][tap * I + i] = bf16(weight), with
 //   forward : o = co, i = ci, weight = w[co][ci][tap]
 //   adjoint : o = ci, i = co, weight = w[co][ci][8 - tap]   (180-degree rotation)
@@ -188,10 +196,26 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
     y0 = (r / tiles_x) * TYF;
     x0 = (r % tiles_x) * TXP;
   };
+  const bool offs_fit = (int64_t)(TYF + 2) * W * CI < ((int64_t)1 << 31);
   auto issue = [&](int tt, int buf) {
     int b, y0, x0;
     coords(tt, b, y0, x0);
     const uint16_t* img = in + (int64_t)b * H * W * CI;
+    if (offs_fit && y0 >= 1 && y0 + TYF + 1 <= H && x0 >= 1 && x0 + TXP + 1 <= W) {
+      // interior tile (no clamping): every copy reads the halo's first pixel
+      // plus an offset given by the copy geometry
+      const uint16_t* base = img + ((int64_t)(y0 - 1) * W + (x0 - 1)) * CI;
+#pragma unroll
+      for (int q = 0; q < QPW; q++) {
+        const int g = wave + 4 * q;
+        if (g < NQ) {
+          const int gq = geo[q];
+          const int off = ((gq >> 16) * W + ((gq >> 8) & 255)) * CI + (gq & 255) * 8;
+          copy16_to_lds(gq >= 0 ? (const void*)(base + off) : zero_page, &halo[buf][g * 64]);
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < QPW; q++) {
       const int g = wave + 4 * q;
@@ -279,8 +303,8 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
                           : dump_page + 4 * kh;
 #pragma unroll
       for (int g = 0; g < 4; g++) {
-        const uint32_t lo = f32_to_bf16(acc[pb][4 * g]) | ((uint32_t)f32_to_bf16(acc[pb][4 * g + 1]) << 16);
-        const uint32_t hi = f32_to_bf16(acc[pb][4 * g + 2]) | ((uint32_t)f32_to_bf16(acc[pb][4 * g + 3]) << 16);
+        const uint32_t lo = pack_bf16x2(acc[pb][4 * g], acc[pb][4 * g + 1]);
+        const uint32_t hi = pack_bf16x2(acc[pb][4 * g + 2], acc[pb][4 * g + 3]);
         *reinterpret_cast<uint2*>(dst + 8 * g) = uint2{lo, hi};
       }
     }
