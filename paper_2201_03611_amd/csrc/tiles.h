@@ -558,7 +558,19 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
                                                  int H, int W, const float* __restrict__ w,
                                                  int zero_pad, int y0, int x0, f32x4* lds) {
   StencilRegs<K, TY> st;
-  if (VEC && (W & 3) == 0) {
+  using Cfg = StencilCfg<K, TY>;
+  if (VEC && y0 >= Cfg::R && y0 + TY + Cfg::R <= H && x0 >= kHalo &&
+      x0 + kStencilTX + kHalo <= W) {
+    // interior tile: no padding, every chunk at a fixed offset from the corner
+    const float* corner = in + (int64_t)(y0 - Cfg::R) * ld_in + (x0 - kHalo);
+#pragma unroll
+    for (int p = 0; p < Cfg::PER; p++) {
+      const int c = min((int)threadIdx.x + p * kThreads, Cfg::LDS_CHUNKS - 1);
+      const int lr = c / kLChunks, cc = c - lr * kLChunks;
+      st[p] = *reinterpret_cast<const f32x4*>(corner + (int64_t)lr * ld_in + 4 * cc);
+    }
+    stencil_stash<K, TY>(st, lds);
+  } else if (VEC && (W & 3) == 0) {
     uint32_t mode;
     stencil_fetch_aligned<K, TY>(st, mode, in, ld_in, H, W, zero_pad, y0, x0);
     stencil_stash_aligned<K, TY>(st, mode, lds);
