@@ -137,14 +137,15 @@ struct FwdCfg {
   static constexpr int NCB = CO / 32;               // cout blocks
   static constexpr int NPB = 1;                     // pixel blocks per wave (registers)
   static constexpr int WPR = NCB * (2 / NPB);       // waves per tile row
-  static constexpr int TYF = 4 / WPR;               // tile rows
+  static constexpr int RPW = WPR == 4 ? 2 : 1;      // rows each wave computes, one after the other
+  static constexpr int TYF = 4 / WPR * RPW;         // tile rows
   static constexpr int KS = TAPS * CI / 16;         // k-steps of 16
   static constexpr int SLOTS = (TYF + 2) * HC * CH; // halo chunks
   static constexpr int NQ = (SLOTS + 63) / 64;      // wave-sized copies per tile
   static constexpr int QPW = (NQ + 3) / 4;          // copies per wave (at most)
-  static constexpr int NBUF = 3;                    // halo ring
+  static constexpr int NBUF = RPW > 1 ? 2 : 3;      // halo ring (two taller tiles fit 2 per CU)
   static constexpr int XPF = CI == 64 ? 3 : 4;      // fragment lookahead (k-steps)
-  static_assert(WPR * TYF == 4, "four waves per tile");
+  static_assert(WPR * TYF == 4 * RPW, "four waves per tile");
 };
 
 template <int CI, int CO>
@@ -156,7 +157,8 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
   using F = FwdCfg<CI, CO>;
   constexpr int CH = F::CH, NPB = F::NPB, NCB = F::NCB, KS = F::KS, NQ = F::NQ, QPW = F::QPW;
   constexpr int TYF = F::TYF, NBUF = F::NBUF, DIST = NBUF - 1;
-  constexpr int NST = 4 * NPB;  // stores per wave per tile
+  constexpr int RPW = F::RPW;
+  constexpr int NST = 4 * NPB * RPW;  // stores per wave per tile
   __shared__ i32x4 halo[NBUF][NQ * 64];  // padded to whole copies; the tail is never read
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -176,19 +178,18 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) wf[ks] = *reinterpret_cast<const bf16x8*>(wr + 16 * ks);
   }
-  // copy geometry, fixed per lane: copy q of this wave fills slots
-  // (wave + 4 q) * 64 + lane = pixel p, physical chunk pc (logical chunk pc ^ key)
-  int geo[QPW];
-#pragma unroll
-  for (int q = 0; q < QPW; q++) {
+  // copy geometry of this lane: copy q of this wave fills slot (wave + 4 q) *
+  // 64 + lane = pixel p, physical chunk pc (logical chunk pc ^ key), packed as
+  // (halo row << 16 | halo column << 8 | logical chunk), -1 past the halo
+  // (recomputed per tile rather than held: it costs a few VALU per copy and
+  // no registers across the k loop)
+  auto geo = [&](int q) {
     const int g = wave + 4 * q, sl = g * 64 + lane;
-    geo[q] = -1;
-    if (g < NQ && sl < F::SLOTS) {
-      const int p = sl / CH, pc = sl % CH;
-      const int c = pc ^ ((p / (16 / CH)) % CH);
-      geo[q] = ((p / HC) << 16) | ((p % HC) << 8) | c;
-    }
-  }
+    if (g >= NQ || sl >= F::SLOTS) return -1;
+    const int p = sl / CH, pc = sl % CH;
+    const int c = pc ^ ((p / (16 / CH)) % CH);
+    return ((p / HC) << 16) | ((p % HC) << 8) | c;
+  };
   auto coords = [&](int tt, int& b, int& y0, int& x0) {
     const int per_img = tiles_x * tiles_y;
     b = tt / per_img;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
       for (int q = 0; q < QPW; q++) {
         const int g = wave + 4 * q;
         if (g < NQ) {
-          const int gq = geo[q];
+          const int gq = geo(q);
           const int off = ((gq >> 16) * W + ((gq >> 8) & 255)) * CI + (gq & 255) * 8;
           copy16_to_lds(gq >= 0 ? (const void*)(base + off) : zero_page, &halo[buf][g * 64]);
         }
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
     for (int q = 0; q < QPW; q++) {
       const int g = wave + 4 * q;
       if (g < NQ) {
-        const int gq = geo[q];
+        const int gq = geo(q);
         const void* src = zero_page;
         if (gq >= 0) {
           int gy = y0 - 1 + (gq >> 16), gx = x0 - 1 + ((gq >> 8) & 255);
@@ -251,63 +252,67 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
     // refill the buffer reduced in the previous iteration, DIST tiles ahead
     issue(min(t + DIST * per, last), (buf + DIST) % NBUF);
 
-    f32x16 acc[NPB];
-#pragma unroll
-    for (int pb = 0; pb < NPB; pb++)
-#pragma unroll
-      for (int r = 0; r < 16; r++) acc[pb][r] = 0.f;
-    // pixel fragments are read XPF k-steps ahead of their MFMA (a ring of
-    // XPF + 1 register slots): one MFMA per k-step is shorter than the LDS
-    // latency, so a one-step lookahead would stall every step
-    constexpr int XPF = F::XPF;
-    bf16x8 xf[XPF + 1][NPB];
-    auto read_x = [&](int ks, int slot) {
-      const int tap = ks / (CI / 16), c16 = ks % (CI / 16);
-      const int dy = tap / 3, dx = tap % 3;
-#pragma unroll
-      for (int pb = 0; pb < NPB; pb++) {
-        const int p = (wrow + dy) * HC + 32 * (wpb * NPB + pb) + il + dx;
-        xf[slot][pb] = __builtin_bit_cast(bf16x8, halo[buf][halo_slot<CH>(p, 2 * c16 + kh)]);
-      }
-    };
-#pragma unroll
-    for (int ks = 0; ks < XPF && ks < KS; ks++) read_x(ks, ks);
-#pragma unroll
-    for (int ks = 0; ks < KS; ks++) {
-      if (ks + XPF < KS) read_x(ks + XPF, (ks + XPF) % (XPF + 1));
+    // the wave's rows of the tile, one after the other (same registers)
+#pragma unroll 1
+    for (int rr = 0; rr < RPW; rr++) {
+      f32x16 acc[NPB];
 #pragma unroll
       for (int pb = 0; pb < NPB; pb++)
-        acc[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[ks], xf[ks % (XPF + 1)][pb], acc[pb],
-                                                          0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[pb][r] = 0.f;
+      // pixel fragments are read XPF k-steps ahead of their MFMA (a ring of
+      // XPF + 1 register slots): one MFMA per k-step is shorter than the LDS
+      // latency, so a one-step lookahead would stall every step
+      constexpr int XPF = F::XPF;
+      bf16x8 xf[XPF + 1][NPB];
+      auto read_x = [&](int ks, int slot) {
+        const int tap = ks / (CI / 16), c16 = ks % (CI / 16);
+        const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+        for (int pb = 0; pb < NPB; pb++) {
+          const int p = (wrow * RPW + rr + dy) * HC + 32 * (wpb * NPB + pb) + il + dx;
+          xf[slot][pb] = __builtin_bit_cast(bf16x8, halo[buf][halo_slot<CH>(p, 2 * c16 + kh)]);
+        }
+      };
+#pragma unroll
+      for (int ks = 0; ks < XPF && ks < KS; ks++) read_x(ks, ks);
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++) {
+        if (ks + XPF < KS) read_x(ks + XPF, (ks + XPF) % (XPF + 1));
+#pragma unroll
+        for (int pb = 0; pb < NPB; pb++)
+          acc[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[ks], xf[ks % (XPF + 1)][pb], acc[pb],
+                                                            0, 0, 0);
+#pragma unroll
+        for (int pb = 0; pb < NPB; pb++) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        }
+      }
+
+      int b, y0, x0;
+      coords(t, b, y0, x0);
+      const int y = y0 + wrow * RPW + rr;
 #pragma unroll
       for (int pb = 0; pb < NPB; pb++) {
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        const int x = x0 + 32 * (wpb * NPB + pb) + il;
+        uint16_t* dst = (y < H && x < W)
+                            ? out + (((int64_t)b * H + y) * W + x) * CO + wcb * 32 + 4 * kh
+                            : dump_page + 4 * kh;
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+          const uint32_t lo = pack_bf16x2(acc[pb][4 * g], acc[pb][4 * g + 1]);
+          const uint32_t hi = pack_bf16x2(acc[pb][4 * g + 2], acc[pb][4 * g + 3]);
+          *reinterpret_cast<uint2*>(dst + 8 * g) = uint2{lo, hi};
+        }
       }
     }
     // the next tile's copies have landed: younger than them are the copies of
-    // DIST - 1 later tiles and the stores of DIST - 1 tiles
+    // DIST - 1 later tiles and the stores of the DIST latest tiles (this one's included)
     if (full_copies)
-      wait_vmcnt<(DIST - 1) * (QPW + NST)>();
+      wait_vmcnt<DIST * NST + (DIST - 1) * QPW>();
     else
-      wait_vmcnt<(DIST - 1) * (QPW - 1 + NST)>();
-
-    int b, y0, x0;
-    coords(t, b, y0, x0);
-    const int y = y0 + wrow;
-#pragma unroll
-    for (int pb = 0; pb < NPB; pb++) {
-      const int x = x0 + 32 * (wpb * NPB + pb) + il;
-      uint16_t* dst = (y < H && x < W)
-                          ? out + (((int64_t)b * H + y) * W + x) * CO + wcb * 32 + 4 * kh
-                          : dump_page + 4 * kh;
-#pragma unroll
-      for (int g = 0; g < 4; g++) {
-        const uint32_t lo = pack_bf16x2(acc[pb][4 * g], acc[pb][4 * g + 1]);
-        const uint32_t hi = pack_bf16x2(acc[pb][4 * g + 2], acc[pb][4 * g + 3]);
-        *reinterpret_cast<uint2*>(dst + 8 * g) = uint2{lo, hi};
-      }
-    }
+      wait_vmcnt<DIST * NST + (DIST - 1) * (QPW - 1)>();
     if (!more) break;
     t = next;
     buf = (buf + 1) % NBUF;
