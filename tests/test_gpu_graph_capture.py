@@ -1,6 +1,7 @@
-"""The multi-launch entry points under HIP graph capture: rise_iterate_sum (two
-kernel passes through the workspace double buffer) and rise_stencil2d_iterate
-(one launch per step, fused steps, and the zero-step copy) are captured once on
+"""Multi-launch entry points under HIP graph capture: rise_iterate_sum (two
+kernel passes through the workspace double buffer), rise_stencil2d_iterate
+(one launch per step, fused steps, and the zero-step copy) and the transposed
+rise_gemv (split-K partials, then their reduction) are captured once on
 a side stream with torch's graph API and replayed several times, with eager
 work and synchronisations between the replays; every replay must reproduce the
 eager result bit for bit (same kernels, same order of additions).  The inputs
@@ -77,3 +78,27 @@ def test_stencil_iterate_replays(rise, k, steps, fuse):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(host(out).view(np.uint32), host(want).view(np.uint32)), rep
+
+
+def test_gemv_transposed_replays(rise):
+    # split-K partials in the workspace, then the fixed-order reduction kernel
+    import torch
+
+    M, K = 3000, 20000
+    A = torch.empty((K, M), device="cuda")
+    x = torch.empty(K, device="cuda")
+    y = torch.empty(M, device="cuda")
+    ws = torch.empty(max(rise.rise_gemv_workspace(M, K, rise.RISE_OP_T), 1), device="cuda",
+                     dtype=torch.uint8)
+    print(f"graph capture gemv transposed M={M} K={K}", flush=True)
+    g = capture(torch, lambda s: rise.rise_gemv(y, A, x, M, K, lda=M, opA=rise.RISE_OP_T, ws=ws,
+                                                stream=s))
+    for rep in range(3):
+        A.copy_(torch.from_numpy(ri.uniform_matrix(ri.rng(9700 + rep), K, M)).cuda())
+        x.copy_(torch.from_numpy(ri.uniform_matrix(ri.rng(9800 + rep), 1, K).reshape(-1)).cuda())
+        want = rise.gemv(A, x, transA=True)
+        torch.cuda.synchronize()
+        y.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(y).view(np.uint32), host(want).view(np.uint32)), rep
