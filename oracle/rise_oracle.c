@@ -14,7 +14,9 @@
  *   - split, join, idx: the DPIA functional primitives of Sec. V-A.  They are
  *     index remappings ("views", Sec. V-C), never materialised here.
  *   - transpose, slide, pad (clamp or zero): not defined in the paper; they get
- *     the standard readings listed in the design doc and are also pure index views.
+ *     their standard readings (transpose swaps two dimensions; slide(sz, sp)
+ *     gives windows of sz elements starting every sp; pad repeats the edge
+ *     element (clamp) or adds zeros) and are also pure index views.
  *   - GEMM is the paper's matrix-vector program (Sec. IV, running example)
  *     mapped over the columns of B:
  *       C = A |> map(aRow => transpose(B) |> map(bCol =>

@@ -2,7 +2,8 @@
 
 split/join follow the DPIA functional primitives (Sec. V-A) and the splitJoinMap
 rewrite (Sec. IV-B); transpose, slide and pad are not defined in the paper and
-follow the readings listed in the design doc.  Every expected value here comes from
+take their standard readings (swap two dimensions; windows of sz elements every
+sp; edge repeat or zeros).  Every expected value here comes from
 numpy slicing or from the law itself, never from the oracle.
 """
 import numpy as np
