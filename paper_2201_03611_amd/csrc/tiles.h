@@ -581,7 +581,7 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
   __syncthreads();
   float wt[K][K];
   stencil_weights<K>(wt, w);
-  stencil_compute_store<K, VEC, TY, false>(out, ld_out, H, W, wt, y0, x0, lds);
+  stencil_compute_store<K, VEC, TY, true>(out, ld_out, H, W, wt, y0, x0, lds);
 }
 
 }  // namespace tiles
