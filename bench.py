@@ -187,6 +187,15 @@ def main():
                              "ms": round(t_sten, 5)},
     }
 
+    # the stencil's events above start when the GEMM ends, so they include the
+    # dispatch gap after it; the same launches back to back (rotating buffers)
+    # give the kernel's own rate beside it
+    ms_b2b = event_ms(torch, stream, lambda: [rise.rise_stencil2d(
+        outs[j], imgs[j], dw, H, W, ld_out=W, ld_in=W, kh=KS, kw=KS, pad="clamp", stream=stream)
+        for j in range(nsets)], 5) / nsets
+    result["roofline_stencil"]["ms_back_to_back"] = round(ms_b2b, 5)
+    result["roofline_stencil"]["achieved_back_to_back"] = round(bytes_sten / (ms_b2b * 1e-3) / 1e9, 1)
+
     if not args.no_precision:
         result["precision"] = precision_leg(rise, ri, np, torch, dev, stream)
     if not args.no_extra:
