@@ -79,6 +79,7 @@ struct StencilArgs {
   const float* w;
   int kh, kw;
   int pad;  // rise_pad
+  bool keep_out = false;  // the output is read again next (normal, not non-temporal, stores)
 };
 int stencil_schedules(rise_stencil_schedule* out, int cap);
 bool stencil_schedule_supported(const rise_stencil_schedule& sc);

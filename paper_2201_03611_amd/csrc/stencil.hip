@@ -35,13 +35,13 @@ using tiles::clampi;
 using tiles::kThreads;
 constexpr int TX = tiles::kStencilTX;  // columns per workgroup / wave strip (64 lanes x 4)
 
-template <int K, bool VEC, int TY>
+template <int K, bool VEC, int TY, bool NT>
 __global__ __launch_bounds__(kThreads) void stencil2d_tiled(
     float* __restrict__ out, int64_t ld_out, const float* __restrict__ in, int64_t ld_in, int H,
     int W, const float* __restrict__ w, int zero_pad, int tiles_x) {
   __shared__ f32x4 lds[tiles::StencilCfg<K, TY>::LDS_CHUNKS];
   const int lid = xcd_contiguous(blockIdx.x, gridDim.x);
-  tiles::stencil_lds_tile<K, VEC, TY>(out, ld_out, in, ld_in, H, W, w, zero_pad,
+  tiles::stencil_lds_tile<K, VEC, TY, NT>(out, ld_out, in, ld_in, H, W, w, zero_pad,
                                       (lid / tiles_x) * TY, (lid % tiles_x) * TX, lds);
 }
 
@@ -387,9 +387,14 @@ __global__ __launch_bounds__(kThreads) void stencil2d_direct(
 template <int K, bool VEC, int TY>
 rise_status launch_tiled(const StencilArgs& a, hipStream_t s) {
   int tiles_x = (a.W + TX - 1) / TX, tiles_y = (a.H + TY - 1) / TY;
-  hipLaunchKernelGGL((stencil2d_tiled<K, VEC, TY>), dim3(tiles_x * tiles_y), dim3(kThreads), 0, s,
-                     a.out, a.ld_out, a.in, a.ld_in, a.H, a.W, a.w, (int)(a.pad == RISE_PAD_ZERO),
-                     tiles_x);
+  if (a.keep_out)
+    hipLaunchKernelGGL((stencil2d_tiled<K, VEC, TY, false>), dim3(tiles_x * tiles_y),
+                       dim3(kThreads), 0, s, a.out, a.ld_out, a.in, a.ld_in, a.H, a.W, a.w,
+                       (int)(a.pad == RISE_PAD_ZERO), tiles_x);
+  else
+    hipLaunchKernelGGL((stencil2d_tiled<K, VEC, TY, true>), dim3(tiles_x * tiles_y),
+                       dim3(kThreads), 0, s, a.out, a.ld_out, a.in, a.ld_in, a.H, a.W, a.w,
+                       (int)(a.pad == RISE_PAD_ZERO), tiles_x);
   return check_launch("stencil2d_tiled");
 }
 

@@ -96,7 +96,7 @@ template <int K>
 __global__ __launch_bounds__(kThreads) void stencil_iter_fused(
     float* __restrict__ out, int64_t ld_out, const float* __restrict__ in, int64_t ld_in, int H,
     int W, const float* __restrict__ w, int zero_pad, int steps, int tiles_x, int ntiles,
-    int per) {
+    int per, int keep_out) {
   using Cfg = ItCfg<K>;
   constexpr int R = Cfg::R, P = Cfg::PITCH;
   __shared__ float lds[2 * Cfg::BUF];
@@ -214,9 +214,13 @@ __global__ __launch_bounds__(kThreads) void stencil_iter_fused(
 #pragma unroll 4
         for (int r = tid >> 7; r < kItTH; r += 2) {
           const int y = y0 + r;
-          if (y < H)
-            __builtin_nontemporal_store(img[(RT + r) * P + R + RT + c],
-                                        out + (int64_t)y * ld_out + x);
+          if (y < H) {
+            const float v = img[(RT + r) * P + R + RT + c];
+            if (keep_out)  // the next launch reads it: leave it in the caches
+              out[(int64_t)y * ld_out + x] = v;
+            else
+              __builtin_nontemporal_store(v, out + (int64_t)y * ld_out + x);
+          }
         }
       }
     }
@@ -247,7 +251,7 @@ rise_status launch_fused(const StencilArgs& a, int steps, hipStream_t s) {
   const int per = (int)std::max<int64_t>(1, (band + rounds - 1) / rounds);
   hipLaunchKernelGGL(stencil_iter_fused<K>, dim3(kNumXcd * per), dim3(kThreads), 0, s, a.out,
                      a.ld_out, a.in, a.ld_in, a.H, a.W, a.w, (int)(a.pad == RISE_PAD_ZERO), steps,
-                     tiles_x, (int)ntiles, per);
+                     tiles_x, (int)ntiles, per, (int)a.keep_out);
   return check_launch("stencil_iter_fused");
 }
 
@@ -294,6 +298,7 @@ rise_status launch_stencil_iterate(const StencilArgs& a, int64_t steps, int fuse
     b.ld_in = ld_src;
     b.out = last ? a.out : buf[i & 1];
     b.ld_out = last ? a.ld_out : a.W;
+    b.keep_out = !last;  // the next launch reads it
     const int n = (int)std::min<int64_t>(fuse, steps - (int64_t)i * fuse);
     rise_status st;
     if (n == 1)

@@ -552,7 +552,9 @@ __device__ __forceinline__ void stencil_weights(float (&wt)[K][K], const float* 
 }
 
 // One tile, start to finish (fetch, stage, barrier, compute, store).
-template <int K, bool VEC, int TY>
+// NT: non-temporal output stores (the output is not read again soon); without
+// it the output stays in the caches for a consumer that reads it next.
+template <int K, bool VEC, int TY, bool NT = true>
 __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_t ld_out,
                                                  const float* __restrict__ in, int64_t ld_in,
                                                  int H, int W, const float* __restrict__ w,
@@ -581,7 +583,7 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
   __syncthreads();
   float wt[K][K];
   stencil_weights<K>(wt, w);
-  stencil_compute_store<K, VEC, TY, true>(out, ld_out, H, W, wt, y0, x0, lds);
+  stencil_compute_store<K, VEC, TY, NT>(out, ld_out, H, W, wt, y0, x0, lds);
 }
 
 }  // namespace tiles
