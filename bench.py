@@ -12,6 +12,8 @@ One JSON line is printed.  Besides the contract fields it carries
   precision         8192^3 GEMM, N(0,1) 2^U(-4,4): time and componentwise error vs
                     the exact product per mode, and the FP32 / BF16X3 speedup
   cpu_baseline      the oracle on a bounded sample of the same workload
+  strategy          beside each result, the schedule the library chose for it
+                    (tile, stencil schedule, passes, K split, steps per launch)
 Kernel times come from HIP events recorded on the stream the kernels run on.
 """
 import argparse
@@ -159,6 +161,9 @@ def main():
     sten_traffic = traffic_for("stencil2d_tiled", ["paper_2201_03611_amd/csrc/stencil.hip",
                                                    "paper_2201_03611_amd/csrc/tiles.h",
                                                    "paper_2201_03611_amd/csrc/common.h"])
+    # the schedules the library chose for the two calls (tile=None, sched=None)
+    gt = rise.rise_gemm_default_tile(M, N, K, "f32")
+    sv, srows = rise.rise_stencil2d_default_schedule(H, W, KS, KS)
     result = {
         "metric": "GEMM TFLOP/s + stencil GB/s vs roofline; BF16-comp vs FP32 speedup at equal error",
         "value": round(value, 3),
@@ -179,13 +184,18 @@ def main():
         "stencil_gbps": round(sten_gbs, 1),
         "roofline": {"bound": "mfma", "achieved": round(gemm_tf, 2), "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": round(gemm_tf / PEAK_FP32_MFMA, 4),
-                     "traffic": gemm_traffic, "kernel": "gemm_f32_kernel<256,128,16>",
+                     "traffic": gemm_traffic,
+                     "kernel": f"gemm_f32_kernel<{gt[0]},{gt[1]},{gt[2]}>",
                      "ms": round(t_gemm, 4)},
         "roofline_stencil": {"bound": "hbm", "achieved": round(sten_gbs, 1), "peak": PEAK_HBM,
                              "unit": "GB/s", "frac": round(sten_gbs / PEAK_HBM, 4),
-                             "traffic": sten_traffic, "kernel": "stencil2d_tiled<5,8 rows>",
+                             "traffic": sten_traffic,
+                             "kernel": f"stencil2d_tiled<{KS},{srows} rows>",
                              "ms": round(t_sten, 5)},
     }
+
+    result["strategy"] = {"gemm": f"f32 tile {gt[0]}x{gt[1]}x{gt[2]}",
+                          "stencil": f"{sv} halo tile, {srows} output rows x 256 columns"}
 
     # the stencil's events above start when the GEMM ends, so they include the
     # dispatch gap after it; the same launches back to back (rotating buffers)
@@ -377,6 +387,13 @@ def batched_leg(rise, ri, torch, dev, stream):
                       "frac_of_overlapped_bound": round(max(t_flop, t_mem) / ms_graph, 3)}
         if ms_sep:
             out[dtype]["speedup_vs_separate"] = round(ms_sep / ms_graph, 2)
+        kinds = {}
+        for i in range(512):
+            t = plan.tile(i)
+            key = f"{t[0]}x{t[1]}x{t[2]}"
+            kinds[key] = kinds.get(key, 0) + 1
+        out[dtype]["strategy"] = {"gemm_tiles": dict(sorted(kinds.items())),
+                                  "stencil": "one resident kernel, LDS halo tiles"}
         plan.destroy()
         del keep
         torch.cuda.empty_cache()
@@ -402,8 +419,11 @@ def gemv_leg(rise, torch, dev, stream):
         ms = event_ms(torch, stream, lambda: rise.rise_gemv(y, A, x, n, n, lda=n, opA=op, ws=ws,
                                                             stream=stream), 20)
         gbs = 4.0 * n * n / (ms * 1e-3) / 1e9
+        parts = rise.rise_gemv_parts(n, n, op)
         res[name] = {"us": round(ms * 1e3, 1), "gbps": round(gbs, 1),
-                     "frac_hbm_peak": round(gbs / PEAK_HBM, 3)}
+                     "frac_hbm_peak": round(gbs / PEAK_HBM, 3),
+                     "strategy": (f"K split in {parts} slices + ordered reduction" if parts > 1
+                                  else "one pass, rows per wavefront")}
     del A
     torch.cuda.empty_cache()
     return res
@@ -429,7 +449,9 @@ def stencil_iterate_leg(rise, ri, torch, dev, stream):
         res[name] = {"ms": round(ms, 3), "us_per_step": round(ms * 1e3 / steps, 1),
                      "gpix_steps_per_s": round(pxs / 1e9, 1),
                      "tflops": round(pxs * 2 * KS * KS / 1e12, 1),
-                     "hbm_gbps_equiv": round(pxs * 8 / 1e9, 1)}
+                     "hbm_gbps_equiv": round(pxs * 8 / 1e9, 1),
+                     "strategy": f"{fuse} step(s) per launch, {-(-steps // fuse)} launches"}
+    res["default_fuse"] = rise.rise_stencil2d_iterate_default_fuse(KS, KS)
     res["fused4"]["frac_fp32_vector_peak"] = round(res["fused4"]["tflops"] / PEAK_F32_VEC, 3)
     res["per_step"]["frac_hbm_peak"] = round(res["per_step"]["hbm_gbps_equiv"] / PEAK_HBM, 3)
     res["speedup_fused"] = round(res["per_step"]["ms"] / res["fused4"]["ms"], 2)
@@ -452,8 +474,10 @@ def iterate_leg(rise, torch, dev, stream):
         ms = event_ms(torch, stream, lambda: rise.rise_iterate_sum(out, x, n, m, k, ws=ws,
                                                                    stream=stream), 20)
         gbs = 4.0 * (total + m) / (ms * 1e-3) / 1e9
+        rounds = rise.rise_iterate_sum_passes(n, m, k)
         res[name] = {"us": round(ms * 1e3, 1), "gbps": round(gbs, 1),
-                     "frac_hbm_peak": round(gbs / PEAK_HBM, 3)}
+                     "frac_hbm_peak": round(gbs / PEAK_HBM, 3),
+                     "strategy": f"{len(rounds)} pass(es), rounds per pass {rounds}"}
         del x
     torch.cuda.empty_cache()
     return res
@@ -490,6 +514,9 @@ def layer_leg(rise, torch, dev, stream):
                      "frac_bf16_peak": round(tf / PEAK_BF16, 3), "gbps": round(gbs, 1),
                      "frac_hbm_peak": round(gbs / PEAK_HBM, 3)}
     res["bound_ms_forward"] = round(max(fl / (PEAK_BF16 * 1e9), 2 * act / (PEAK_HBM * 1e6)), 3)
+    res["strategy"] = {"forward": "bf16 MFMA, weights in registers, halo tiles of two rows per wave",
+                       "dIn": "the forward kernel with rotated, channel-transposed weights",
+                       "dW": "per-workgroup partial sums over pixel tiles + ordered reduction"}
     return res
 
 
@@ -530,7 +557,9 @@ def precision_leg(rise, ri, np, torch, dev, stream):
         # outputs with |c| >= 1e-3 max|c| (both over the same samples)
         big = np.abs(exact) >= 1e-3 * np.max(np.abs(exact))
         tf = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        tl = rise.rise_gemm_default_tile(n, n, n, mode)
         out[mode] = {"ms": round(ms, 3), "tflops_useful": round(tf, 1),
+                     "strategy": f"{mode} tile {tl[0]}x{tl[1]}x{tl[2]}",
                      "frac_of_own_peak": round(tf / peaks[mode], 4),
                      "err_componentwise_max": err,
                      "err_normwise": float(np.max(diff) / np.max(np.abs(exact))),

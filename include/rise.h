@@ -87,6 +87,15 @@ const char* rise_last_error(void);
  * them are written there.  Host-only, enqueues nothing. */
 int32_t rise_gemm_tiles(rise_mode mode, rise_tile* out, int32_t cap);
 
+/* The strategy rise_gemm applies when its `tile` argument is NULL: writes to
+ * *out the tile the library picks for these sizes and mode (Sec. IV-B/C leave
+ * that choice to a strategy outside the program; this reports it).  Host-only,
+ * enqueues nothing.  Errors: sizes outside [0, 2^31) (RISE_ERR_SHAPE), an
+ * unknown mode (RISE_ERR_UNSUPPORTED), out NULL (RISE_ERR_NULL); *out is then
+ * left unchanged. */
+rise_status rise_gemm_default_tile(int64_t M, int64_t N, int64_t K, rise_mode mode,
+                                   rise_tile* out);
+
 /* ------------------------------------------------------------------------ */
 /* GEMM                                                                     */
 /* ------------------------------------------------------------------------ */
@@ -131,6 +140,12 @@ size_t rise_gemv_workspace(int64_t M, int64_t K, rise_op opA);
 rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const float* x,
                       int64_t M, int64_t K, void* ws, size_t ws_bytes, void* stream);
 
+/* The schedule rise_gemv runs for these sizes: the number of slices the
+ * reduction over K is split into (1 = one kernel writes y; more = each slice's
+ * partial sums go to the workspace and a second kernel adds them in slice
+ * order).  Always 1 for RISE_OP_N.  Host-only; 0 for invalid sizes or opA. */
+int32_t rise_gemv_parts(int64_t M, int64_t K, rise_op opA);
+
 /* iterate (Sec. VI) with the tree-reduction body:
  *   out = iterate(n, m, k, split(n) |> map(reduce(+, 0)), in)
  * in: n^k * m floats (device), out: m floats (device).  Each of the k rounds
@@ -150,6 +165,14 @@ rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const 
 size_t rise_iterate_sum_workspace(int64_t n, int64_t m, int64_t k);
 rise_status rise_iterate_sum(float* out, const float* in, int64_t n, int64_t m, int64_t k,
                              void* ws, size_t ws_bytes, void* stream);
+
+/* How rise_iterate_sum compiles iterate (Sec. VI) for these sizes: returns the
+ * number of kernel passes (each runs several rounds inside LDS; consecutive
+ * passes ping-pong through the workspace halves) and writes the rounds of
+ * each pass to rounds[0 .. min(passes, cap)) when rounds is non-NULL.  For
+ * n > 1 the rounds add up to k; n = 1 runs one round.  Host-only; 0 when the
+ * sizes are outside rise_iterate_sum's limits or m = 0. */
+int32_t rise_iterate_sum_passes(int64_t n, int64_t m, int64_t k, int32_t* rounds, int32_t cap);
 
 /* Gradients of L(C) with C = A . B (A: M x K, B: K x N, row-major FP32):
  *   dA = dC . transpose(B)   (M x K)     dB = transpose(A) . dC   (K x N)
@@ -218,6 +241,15 @@ typedef struct {
  * Host-only. */
 int32_t rise_stencil_schedules(rise_stencil_schedule* out, int32_t cap);
 
+/* The schedule rise_stencil2d runs when its `sched` argument is NULL, written
+ * to *out (a strategy's choice, Sec. IV-B/C, reported).  Windows other than
+ * square 1, 3, 5 and 7 run the direct per-output kernel, reported as
+ * variant -1, rows 0.  Host-only, enqueues nothing.  Errors: sizes outside
+ * [0, 2^31) (RISE_ERR_SHAPE), even or oversized window sides
+ * (RISE_ERR_UNSUPPORTED), out NULL (RISE_ERR_NULL). */
+rise_status rise_stencil2d_default_schedule(int64_t H, int64_t W, int32_t kh, int32_t kw,
+                                            rise_stencil_schedule* out);
+
 /* out = in |> pad2D(pad) |> slide2D(kh x kw, 1)
  *          |> map(map(win => zip(join(win), join(w)) |> map(*) |> reduce(+, 0)))
  * in: H x W FP32 (ld_in), out: H x W FP32 (ld_out), w: kh x kw FP32 weights,
@@ -253,6 +285,8 @@ rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t 
  * rise_stencil2d, plus steps < 0, an unknown fuse, and a short, misaligned or
  * overlapping workspace. */
 int32_t rise_stencil2d_iterate_max_fuse(void);
+/* The steps per launch that fuse = 0 selects for this window (host-only). */
+int32_t rise_stencil2d_iterate_default_fuse(int32_t kh, int32_t kw);
 size_t rise_stencil2d_iterate_workspace(int64_t H, int64_t W, int32_t kh, int32_t kw,
                                         int64_t steps, int32_t fuse);
 rise_status rise_stencil2d_iterate(float* out, int64_t ld_out, const float* in, int64_t ld_in,

@@ -83,6 +83,14 @@ def rise_gemm_tiles(mode):
     return [(arr[i].bm, arr[i].bn, arr[i].bk) for i in range(n)]
 
 
+def rise_gemm_default_tile(M, N, K, mode="f32"):
+    """The tile rise_gemm runs with tile=None, as (bm, bn, bk)."""
+    t = RiseTile()
+    _check(lib.rise_gemm_default_tile(M, N, K, _mode(mode), ctypes.byref(t)),
+           "rise_gemm_default_tile")
+    return (t.bm, t.bn, t.bk)
+
+
 def rise_gemm_workspace(M, N, K, mode, tile=None):
     return int(lib.rise_gemm_workspace(M, N, K, _mode(mode), _tile(tile)))
 
@@ -101,6 +109,10 @@ def rise_gemv_workspace(M, K, opA=RISE_OP_N):
     return int(lib.rise_gemv_workspace(M, K, opA))
 
 
+def rise_gemv_parts(M, K, opA=RISE_OP_N):
+    return int(lib.rise_gemv_parts(M, K, opA))
+
+
 def rise_gemv(y, A, x, M, K, *, lda, opA=RISE_OP_N, ws=None, stream=None):
     """y (M floats) = A . x, A read through opA (the paper's matrix-vector program)."""
     _require_cuda(y, A, x, ws)
@@ -112,6 +124,14 @@ def rise_gemv(y, A, x, M, K, *, lda, opA=RISE_OP_N, ws=None, stream=None):
 
 def rise_iterate_sum_workspace(n, m, k):
     return int(lib.rise_iterate_sum_workspace(n, m, k))
+
+
+def rise_iterate_sum_passes(n, m, k):
+    """Rounds run by each kernel pass of rise_iterate_sum ([] for invalid sizes)."""
+    np_ = lib.rise_iterate_sum_passes(n, m, k, None, 0)
+    arr = (ctypes.c_int32 * max(np_, 1))()
+    lib.rise_iterate_sum_passes(n, m, k, arr, np_)
+    return [int(arr[i]) for i in range(np_)]
 
 
 def rise_iterate_sum(out, x, n, m, k, *, ws=None, stream=None):
@@ -159,6 +179,18 @@ def rise_stencil_schedules():
     return [(names[arr[i].variant], arr[i].rows) for i in range(n)]
 
 
+def rise_stencil2d_default_schedule(H, W, kh, kw):
+    """The schedule rise_stencil2d runs with schedule=None, as (name, rows);
+    ("direct", 0) for windows the scheduled kernels do not cover."""
+    sc = RiseStencilSchedule()
+    _check(lib.rise_stencil2d_default_schedule(H, W, kh, kw, ctypes.byref(sc)),
+           "rise_stencil2d_default_schedule")
+    if sc.variant < 0:
+        return ("direct", 0)
+    names = {v: k for k, v in SCHEDULES.items()}
+    return (names[sc.variant], sc.rows)
+
+
 def _sched(sc):
     if sc is None:
         return None
@@ -177,6 +209,10 @@ def rise_stencil2d(out, inp, w, H, W, *, ld_out, ld_in, kh, kw, pad="clamp", sch
 
 def rise_stencil2d_iterate_max_fuse():
     return int(lib.rise_stencil2d_iterate_max_fuse())
+
+
+def rise_stencil2d_iterate_default_fuse(kh, kw):
+    return int(lib.rise_stencil2d_iterate_default_fuse(kh, kw))
 
 
 def rise_stencil2d_iterate_workspace(H, W, kh, kw, steps, fuse=0):

@@ -53,16 +53,20 @@ _INT = ctypes.c_int
 # name -> (restype, argtypes)
 SIGNATURES = {
     "rise_gemv_workspace": (_SZ, [_I64, _I64, _INT]),
+    "rise_gemv_parts": (_I32, [_I64, _I64, _INT]),
     "rise_gemv": (_INT, [_P, _P, _I64, _INT, _P, _I64, _I64, _P, _SZ, _P]),
     "rise_stencil2d_iterate_max_fuse": (_INT, []),
+    "rise_stencil2d_iterate_default_fuse": (_I32, [_I32, _I32]),
     "rise_stencil2d_iterate_workspace": (_SZ, [_I64, _I64, _INT, _INT, _I64, _INT]),
     "rise_stencil2d_iterate": (_INT, [_P, _I64, _P, _I64, _I64, _I64, _P, _INT, _INT, _INT, _I64,
                                       _INT, _P, _SZ, _P]),
     "rise_iterate_sum_workspace": (_SZ, [_I64, _I64, _I64]),
+    "rise_iterate_sum_passes": (_I32, [_I64, _I64, _I64, ctypes.POINTER(_I32), _I32]),
     "rise_iterate_sum": (_INT, [_P, _P, _I64, _I64, _I64, _P, _SZ, _P]),
     "rise_status_string": (ctypes.c_char_p, [_INT]),
     "rise_last_error": (ctypes.c_char_p, []),
     "rise_gemm_tiles": (_I32, [_INT, ctypes.POINTER(RiseTile), _I32]),
+    "rise_gemm_default_tile": (_INT, [_I64, _I64, _I64, _INT, ctypes.POINTER(RiseTile)]),
     "rise_gemm_workspace": (_SZ, [_I64, _I64, _I64, _INT, ctypes.POINTER(RiseTile)]),
     "rise_gemm": (_INT, [_P, _I64, _P, _INT, _I64, _INT, _P, _INT, _I64, _INT, _I64, _I64, _I64,
                          _INT, ctypes.POINTER(RiseTile), _P, _SZ, _P]),
@@ -72,6 +76,8 @@ SIGNATURES = {
     "rise_prep_bytes": (_SZ, [_I64, _I64, _INT]),
     "rise_prep_operand": (_INT, [_P, _I64, _I64, _P, _I64, _I64, _I64, _I64, _INT, _P]),
     "rise_stencil_schedules": (_I32, [ctypes.POINTER(RiseStencilSchedule), _I32]),
+    "rise_stencil2d_default_schedule": (_INT, [_I64, _I64, _I32, _I32,
+                                                ctypes.POINTER(RiseStencilSchedule)]),
     "rise_stencil2d": (_INT, [_P, _I64, _P, _I64, _I64, _I64, _P, _I32, _I32, _INT,
                               ctypes.POINTER(RiseStencilSchedule), _P]),
     "rise_conv2d_workspace": (_SZ, [_I32, _I32]),

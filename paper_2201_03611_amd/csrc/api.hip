@@ -97,6 +97,19 @@ int32_t rise_gemm_tiles(rise_mode mode, rise_tile* out, int32_t cap) {
   return gemm_lowp_tiles(mode, out, cap);
 }
 
+rise_status rise_gemm_default_tile(int64_t M, int64_t N, int64_t K, rise_mode mode,
+                                   rise_tile* out) {
+  clear_error();
+  if (!dim_ok(M) || !dim_ok(N) || !dim_ok(K))
+    return fail(RISE_ERR_SHAPE, "rise_gemm_default_tile: sizes must be in [0, 2^31)");
+  if (mode < RISE_MODE_F32 || mode > RISE_MODE_FP8)
+    return fail(RISE_ERR_UNSUPPORTED, "rise_gemm_default_tile: unknown mode");
+  if (!out) return fail(RISE_ERR_NULL, "rise_gemm_default_tile: out is NULL");
+  *out = mode == RISE_MODE_F32 ? gemm_f32_default_tile((int)M, (int)N, (int)K)
+                               : gemm_lowp_default_tile(mode, (int)M, (int)N, (int)K);
+  return RISE_OK;
+}
+
 size_t rise_gemm_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode,
                            const rise_tile* tile) {
   if (mode == RISE_MODE_F32) return 0;
@@ -202,6 +215,21 @@ int32_t rise_stencil_schedules(rise_stencil_schedule* out, int32_t cap) {
   return stencil_schedules(out, cap);
 }
 
+rise_status rise_stencil2d_default_schedule(int64_t H, int64_t W, int32_t kh, int32_t kw,
+                                            rise_stencil_schedule* out) {
+  clear_error();
+  if (!dim_ok(H) || !dim_ok(W))
+    return fail(RISE_ERR_SHAPE, "rise_stencil2d_default_schedule: sizes must be in [0, 2^31)");
+  if (kh <= 0 || kw <= 0 || kh % 2 == 0 || kw % 2 == 0 || kh > 15 || kw > 15)
+    return fail(RISE_ERR_UNSUPPORTED,
+                "rise_stencil2d_default_schedule: window sides must be odd and <= 15");
+  if (!out) return fail(RISE_ERR_NULL, "rise_stencil2d_default_schedule: out is NULL");
+  const bool scheduled = kh == kw && (kh == 1 || kh == 3 || kh == 5 || kh == 7);
+  *out = scheduled ? stencil_default_schedule((int)H, (int)W, kh, kw)
+                   : rise_stencil_schedule{-1, 0};
+  return RISE_OK;
+}
+
 rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t ld_in,
                            int64_t H, int64_t W, const float* w, int32_t kh, int32_t kw,
                            rise_pad pad, const rise_stencil_schedule* sched, void* stream) {
@@ -234,6 +262,10 @@ static int iterate_fuse(int32_t kh, int32_t kw, int32_t fuse) {
   if (fuse < 0 || fuse > stencil_iterate_max_fuse() || !stencil_iterate_fusable(kh, kw))
     return -1;
   return fuse;
+}
+
+int32_t rise_stencil2d_iterate_default_fuse(int32_t kh, int32_t kw) {
+  return stencil_iterate_default_fuse(kh, kw);
 }
 
 size_t rise_stencil2d_iterate_workspace(int64_t H, int64_t W, int32_t kh, int32_t kw,
@@ -281,6 +313,11 @@ rise_status rise_stencil2d_iterate(float* out, int64_t ld_out, const float* in, 
   }
   StencilArgs a{out, ld_out, in, ld_in, (int)H, (int)W, w, kh, kw, (int)pad};
   return launch_stencil_iterate(a, steps, f, ws, (hipStream_t)stream);
+}
+
+int32_t rise_gemv_parts(int64_t M, int64_t K, rise_op opA) {
+  if (!dim_ok(M) || !dim_ok(K) || (opA != RISE_OP_N && opA != RISE_OP_T)) return 0;
+  return gemv_parts(M, K, opA == RISE_OP_T);
 }
 
 size_t rise_gemv_workspace(int64_t M, int64_t K, rise_op opA) {
@@ -335,6 +372,12 @@ static int64_t iterate_len(int64_t n, int64_t m, int64_t k) {
 size_t rise_iterate_sum_workspace(int64_t n, int64_t m, int64_t k) {
   if (iterate_len(n, m, k) < 0 || n > iterate_max_fan_in() || m == 0) return 0;
   return iterate_sum_workspace(n, m, k);
+}
+
+int32_t rise_iterate_sum_passes(int64_t n, int64_t m, int64_t k, int32_t* rounds,
+                                int32_t cap) {
+  if (iterate_len(n, m, k) < 0 || n > iterate_max_fan_in() || m == 0) return 0;
+  return iterate_sum_rounds(n, m, k, rounds, cap < 0 ? 0 : cap);
 }
 
 rise_status rise_iterate_sum(float* out, const float* in, int64_t n, int64_t m, int64_t k,

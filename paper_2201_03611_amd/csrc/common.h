@@ -113,6 +113,7 @@ struct GemvArgs {
   int M, K;
 };
 size_t gemv_workspace(int64_t M, int64_t K, bool trans);
+int gemv_parts(int64_t M, int64_t K, bool trans);
 rise_status launch_gemv(const GemvArgs& a, void* ws, hipStream_t s);
 rise_status launch_stencil2d_backward(const StencilBwdArgs& a, void* ws, hipStream_t s);
 
@@ -131,6 +132,7 @@ rise_status launch_stencil_iterate(const StencilArgs& a, int64_t steps, int fuse
 // ---------------------------------------------------------------------------
 int iterate_max_fan_in();
 size_t iterate_sum_workspace(int64_t n, int64_t m, int64_t k);
+int iterate_sum_rounds(int64_t n, int64_t m, int64_t k, int32_t* rounds, int cap);
 rise_status launch_iterate_sum(float* out, const float* in, int64_t n, int64_t m, int64_t k,
                                void* ws, hipStream_t s);
 

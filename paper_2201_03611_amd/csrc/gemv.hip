@@ -192,6 +192,11 @@ size_t gemv_workspace(int64_t M, int64_t K, bool trans) {
   return c.kchunks > 1 ? (size_t)c.kchunks * M * 4 : 0;
 }
 
+int gemv_parts(int64_t M, int64_t K, bool trans) {
+  if (!trans || M == 0 || K == 0) return 1;
+  return col_split(M, K).kchunks;
+}
+
 rise_status launch_gemv(const GemvArgs& a, void* ws, hipStream_t s) {
   // K = 0 needs no special case: the kernels reduce over an empty range and
   // store the initial value 0

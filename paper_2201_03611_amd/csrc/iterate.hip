@@ -235,6 +235,13 @@ size_t iterate_sum_workspace(int64_t n, int64_t m, int64_t k) {
   return 2 * half;
 }
 
+int iterate_sum_rounds(int64_t n, int64_t m, int64_t k, int32_t* rounds, int cap) {
+  Pass ps[kMaxPasses];
+  const int np = plan(n, m, k, ps, kMaxPasses);
+  for (int i = 0; rounds && i < np && i < cap; i++) rounds[i] = ps[i].L;
+  return np;
+}
+
 rise_status launch_iterate_sum(float* out, const float* in, int64_t n, int64_t m, int64_t k,
                                void* ws, hipStream_t s) {
   Pass ps[kMaxPasses];

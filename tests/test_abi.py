@@ -179,6 +179,53 @@ def test_tiles_and_workspace_queries(lib):
     assert lib.rise_prep_bytes(64, 64, 3) == 3 * 64 * 64 * 2
 
 
+def test_strategy_queries():
+    """The schedules the library picks when the caller leaves the choice to it
+    (Sec. IV-B/C), reported by host-only queries."""
+    import paper_2201_03611_amd as rise
+
+    for mode in ("f32", "bf16", "bf16x3", "bf16x6", "fp8"):
+        for mnk in ((4096, 4096, 4096), (64, 64, 64), (1000, 3000, 77), (0, 0, 0)):
+            assert rise.rise_gemm_default_tile(*mnk, mode) in rise.rise_gemm_tiles(mode)
+    assert rise.rise_gemm_default_tile(4096, 4096, 4096, "f32") == (256, 128, 16)
+    with pytest.raises(rise.RiseError):
+        rise.rise_gemm_default_tile(-1, 4, 4, "f32")
+
+    scheds = rise.rise_stencil_schedules()
+    assert rise.rise_stencil2d_default_schedule(4096, 4096, 5, 5) == ("lds", 8)
+    assert rise.rise_stencil2d_default_schedule(4096, 4096, 7, 7) == ("lds", 16)
+    for k in (1, 3, 5, 7):
+        assert rise.rise_stencil2d_default_schedule(300, 517, k, k) in scheds
+    assert rise.rise_stencil2d_default_schedule(64, 64, 9, 9) == ("direct", 0)
+    assert rise.rise_stencil2d_default_schedule(64, 64, 3, 5) == ("direct", 0)
+    with pytest.raises(rise.RiseError):
+        rise.rise_stencil2d_default_schedule(64, 64, 4, 4)
+
+    assert rise.rise_stencil2d_iterate_default_fuse(3, 3) == rise.rise_stencil2d_iterate_max_fuse()
+    assert rise.rise_stencil2d_iterate_default_fuse(5, 5) == 1
+    assert rise.rise_stencil2d_iterate_default_fuse(7, 7) == 1
+
+    # every pass sums groups of n^rounds <= 8192 values inside one workgroup;
+    # the passes together run all k rounds
+    for n, m, k in ((2, 1, 26), (2, 4096, 14), (4, 3, 9), (3, 5, 7), (8192, 2, 2), (2, 7, 0)):
+        rounds = rise.rise_iterate_sum_passes(n, m, k)
+        assert sum(rounds) == k and all(n ** r <= 8192 for r in rounds), (n, m, k, rounds)
+        assert (len(rounds) > 1) == (rise.rise_iterate_sum_workspace(n, m, k) > 0)
+    assert rise.rise_iterate_sum_passes(2, 1, 26) == [13, 13]
+    assert rise.rise_iterate_sum_passes(1, 4, 9) == [1]
+    assert rise.rise_iterate_sum_passes(2, 0, 5) == []
+    assert rise.rise_iterate_sum_passes(8193, 1, 1) == []
+
+    for M, K in ((16384, 16384), (3000, 20000), (64, 64), (5, 0)):
+        assert rise.rise_gemv_parts(M, K, rise.RISE_OP_N) == 1
+        parts = rise.rise_gemv_parts(M, K, rise.RISE_OP_T)
+        ws = rise.rise_gemv_workspace(M, K, rise.RISE_OP_T)
+        assert parts >= 1 and (parts > 1) == (ws > 0)
+        if parts > 1:
+            assert ws == (parts * M * 4 + 255) // 256 * 256
+    assert rise.rise_gemv_parts(-1, 4, rise.RISE_OP_T) == 0
+
+
 def stencil(lib, out=FAKE_C, ld_out=100, inp=FAKE_A, ld_in=100, H=50, W=100, w=FAKE_W, kh=5,
             kw=5, pad=0, sched=None):
     return lib.rise_stencil2d(out, ld_out, inp, ld_in, H, W, w, kh, kw, pad, sched, None)
