@@ -72,6 +72,28 @@ def _require_cuda(*ts):
             raise ValueError("librise works on device tensors only")
 
 
+def _require_dtype(t, dtype, what):
+    if t is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+
+
+def _on_stream(fn):
+    """Run a convenience wrapper with `stream` as torch's current stream, so that
+    its input copies, its output and workspace allocations and the library call
+    all belong to that stream (the caching allocator then cannot hand the
+    workspace to another allocation while the kernel still reads it)."""
+    import functools
+
+    @functools.wraps(fn)
+    def wrapper(*args, stream=None, **kwargs):
+        if stream is None:
+            return fn(*args, **kwargs)
+        with torch.cuda.stream(stream):
+            return fn(*args, **kwargs)
+
+    return wrapper
+
+
 # ---------------------------------------------------------------------------
 # one-to-one entry points
 # ---------------------------------------------------------------------------
@@ -346,9 +368,14 @@ class Plan:
 # ---------------------------------------------------------------------------
 # convenience wrappers
 # ---------------------------------------------------------------------------
-def gemm(A, B, *, transA=False, transB=False, mode="f32", tile=None, out=None, ws=None,
-         stream=None):
-    """Logical A (M x K) times logical B (K x N); transA means A is stored K x M."""
+@_on_stream
+def gemm(A, B, *, transA=False, transB=False, mode="f32", tile=None, out=None, ws=None):
+    """Logical A (M x K) times logical B (K x N); transA means A is stored K x M.
+    A and B are float32, or bfloat16 for mode "bf16"."""
+    for t, nm in ((A, "A"), (B, "B")):
+        if t.dtype not in (torch.float32, torch.bfloat16):
+            raise TypeError(f"{nm} must be float32 or bfloat16, got {t.dtype}")
+    _require_cuda(A, B)
     A = A.contiguous()
     B = B.contiguous()
     M, K = (A.shape[1], A.shape[0]) if transA else A.shape
@@ -362,26 +389,36 @@ def gemm(A, B, *, transA=False, transB=False, mode="f32", tile=None, out=None, w
         ws = torch.empty(need, device=A.device, dtype=torch.uint8)
     rise_gemm(out, A, B, M, N, K, lda=A.shape[1], ldb=B.shape[1], ldc=out.stride(0),
               opA=RISE_OP_T if transA else RISE_OP_N, opB=RISE_OP_T if transB else RISE_OP_N,
-              mode=mode, tile=tile, ws=ws, stream=stream)
+              mode=mode, tile=tile, ws=ws)
     return out
 
 
-def gemv(A, x, *, transA=False, out=None, stream=None):
+@_on_stream
+def gemv(A, x, *, transA=False, out=None):
     """y = A . x for a 2-D float32 device tensor A (read transposed if transA) and a
     vector x; allocates y and the workspace with torch."""
+    _require_dtype(A, torch.float32, "A")
+    _require_dtype(x, torch.float32, "x")
     _require_cuda(A, x)
+    A = A.contiguous()
+    x = x.contiguous().reshape(-1)
     M, K = (A.shape[1], A.shape[0]) if transA else A.shape
     op = RISE_OP_T if transA else RISE_OP_N
     y = out if out is not None else torch.empty(M, device=A.device, dtype=torch.float32)
     n = rise_gemv_workspace(M, K, op)
     ws = torch.empty(n, device=A.device, dtype=torch.uint8) if n else None
-    rise_gemv(y, A, x, M, K, lda=A.stride(0), opA=op, ws=ws, stream=stream)
+    if x.numel() != K:
+        raise ValueError(f"x has {x.numel()} values, A has {K} columns")
+    rise_gemv(y, A, x, M, K, lda=A.stride(0), opA=op, ws=ws)
     return y
 
 
-def stencil2d_iterate(img, w, steps, pad="clamp", fuse=0, out=None, stream=None):
+@_on_stream
+def stencil2d_iterate(img, w, steps, pad="clamp", fuse=0, out=None):
     """`steps` applications of the 2D stencil to a float32 device image; allocates
     the output and the double-buffer workspace with torch."""
+    _require_dtype(img, torch.float32, "img")
+    _require_cuda(img, w)
     img = img.contiguous()
     w = w.contiguous().to(device=img.device, dtype=torch.float32)
     H, W = img.shape
@@ -391,13 +428,15 @@ def stencil2d_iterate(img, w, steps, pad="clamp", fuse=0, out=None, stream=None)
     need = rise_stencil2d_iterate_workspace(H, W, kh, kw, steps, fuse)
     ws = torch.empty(need, device=img.device, dtype=torch.uint8) if need else None
     rise_stencil2d_iterate(out, img, w, H, W, ld_out=out.stride(0), ld_in=W, kh=kh, kw=kw,
-                           steps=steps, pad=pad, fuse=fuse, ws=ws, stream=stream)
+                           steps=steps, pad=pad, fuse=fuse, ws=ws)
     return out
 
 
-def iterate_sum(x, n, k, *, out=None, stream=None):
+@_on_stream
+def iterate_sum(x, n, k, *, out=None):
     """Tree reduction of a float32 device tensor by iterate (Sec. VI): k rounds of
     summing groups of n neighbours; x.numel() must be n^k * m, returns m values."""
+    _require_dtype(x, torch.float32, "x")
     _require_cuda(x)
     x = x.contiguous().reshape(-1)
     G = int(n) ** int(k)
@@ -407,11 +446,14 @@ def iterate_sum(x, n, k, *, out=None, stream=None):
     y = out if out is not None else torch.empty(m, device=x.device, dtype=torch.float32)
     need = rise_iterate_sum_workspace(n, m, k)
     ws = torch.empty(need, device=x.device, dtype=torch.uint8) if need else None
-    rise_iterate_sum(y, x, n, m, k, ws=ws, stream=stream)
+    rise_iterate_sum(y, x, n, m, k, ws=ws)
     return y
 
 
-def stencil2d(img, w, pad="clamp", out=None, schedule=None, stream=None):
+@_on_stream
+def stencil2d(img, w, pad="clamp", out=None, schedule=None):
+    _require_dtype(img, torch.float32, "img")
+    _require_cuda(img, w)
     img = img.contiguous()
     w = w.contiguous().to(device=img.device, dtype=torch.float32)
     H, W = img.shape
@@ -419,21 +461,28 @@ def stencil2d(img, w, pad="clamp", out=None, schedule=None, stream=None):
     if out is None:
         out = torch.empty((H, W), device=img.device, dtype=torch.float32)
     rise_stencil2d(out, img, w, H, W, ld_out=out.stride(0), ld_in=img.stride(0), kh=kh, kw=kw,
-                   pad=pad, schedule=schedule, stream=stream)
+                   pad=pad, schedule=schedule)
     return out
 
 
-def prep_operand(src, mode, *, rows, K, ld_r, ld_k, rows_out=None, k_out=None, stream=None):
+@_on_stream
+def prep_operand(src, mode, *, rows, K, ld_r, ld_k, rows_out=None, k_out=None):
+    _require_dtype(src, torch.float32, "src")
+    _require_cuda(src)
     rows_out = rows if rows_out is None else rows_out
     k_out = K if k_out is None else k_out
     out = torch.empty(rise_prep_bytes(rows_out, k_out, mode), device=src.device,
                       dtype=torch.uint8)
-    rise_prep_operand(out, rows_out, k_out, src, rows, K, ld_r, ld_k, mode, stream=stream)
+    rise_prep_operand(out, rows_out, k_out, src, rows, K, ld_r, ld_k, mode)
     return out
 
 
-def gemm_backward(dC, A, B, *, mode="f32", need_dA=True, need_dB=True, stream=None):
+@_on_stream
+def gemm_backward(dC, A, B, *, mode="f32", need_dA=True, need_dB=True):
     """(dA, dB) of C = A . B for row-major FP32 A (M x K), B (K x N), dC (M x N)."""
+    for t, nm in ((dC, "dC"), (A, "A"), (B, "B")):
+        _require_dtype(t, torch.float32, nm)
+    _require_cuda(dC, A, B)
     dC, A, B = dC.contiguous(), A.contiguous(), B.contiguous()
     M, K = A.shape
     N = B.shape[1]
@@ -442,11 +491,15 @@ def gemm_backward(dC, A, B, *, mode="f32", need_dA=True, need_dB=True, stream=No
     need = rise_gemm_backward_workspace(M, N, K, mode)
     ws = torch.empty(need, device=A.device, dtype=torch.uint8) if need else None
     rise_gemm_backward(dA, dB, dC, A, B, M, N, K, ldda=K, lddb=N, lddc=N, lda=K, ldb=N,
-                       mode=mode, ws=ws, stream=stream)
+                       mode=mode, ws=ws)
     return dA, dB
 
 
-def stencil2d_backward(dOut, img, w, pad="clamp", *, need_din=True, need_dw=True, stream=None):
+@_on_stream
+def stencil2d_backward(dOut, img, w, pad="clamp", *, need_din=True, need_dw=True):
+    _require_dtype(dOut, torch.float32, "dOut")
+    _require_dtype(img, torch.float32, "img")
+    _require_cuda(dOut, img, w)
     dOut, img = dOut.contiguous(), img.contiguous()
     w = w.contiguous().to(device=img.device, dtype=torch.float32)
     H, W = img.shape
@@ -456,24 +509,30 @@ def stencil2d_backward(dOut, img, w, pad="clamp", *, need_din=True, need_dw=True
     ws = torch.empty(max(rise_stencil2d_backward_workspace(H, W, kh, kw), 256), device=img.device,
                      dtype=torch.uint8)
     rise_stencil2d_backward(dIn, dW, dOut, img, w, H, W, ld_din=W, ld_dout=W, ld_in=W, kh=kh,
-                            kw=kw, pad=pad, ws=ws, stream=stream)
+                            kw=kw, pad=pad, ws=ws)
     return dIn, dW
 
 
-def conv2d(x, w, pad="zero", stream=None):
+@_on_stream
+def conv2d(x, w, pad="zero"):
     """x: B x H x W x Cin bfloat16 (NHWC), w: Cout x Cin x 3 x 3 float32 -> bfloat16 NHWC."""
+    _require_dtype(x, torch.bfloat16, "x")
+    _require_cuda(x, w)
     x = x.contiguous()
     w = w.contiguous().to(device=x.device, dtype=torch.float32)
     B, H, W, Cin = x.shape
     Cout = w.shape[0]
     out = torch.empty((B, H, W, Cout), device=x.device, dtype=torch.bfloat16)
     ws = torch.empty(rise_conv2d_workspace(Cin, Cout), device=x.device, dtype=torch.uint8)
-    rise_conv2d(out, x, w, B, Cin, Cout, H, W, kh=w.shape[2], kw=w.shape[3], pad=pad, ws=ws,
-                stream=stream)
+    rise_conv2d(out, x, w, B, Cin, Cout, H, W, kh=w.shape[2], kw=w.shape[3], pad=pad, ws=ws)
     return out
 
 
-def conv2d_backward(dOut, x, w, pad="zero", *, need_din=True, need_dw=True, stream=None):
+@_on_stream
+def conv2d_backward(dOut, x, w, pad="zero", *, need_din=True, need_dw=True):
+    _require_dtype(dOut, torch.bfloat16, "dOut")
+    _require_dtype(x, torch.bfloat16, "x")
+    _require_cuda(dOut, x, w)
     dOut, x = dOut.contiguous(), x.contiguous()
     w = w.contiguous().to(device=x.device, dtype=torch.float32)
     B, H, W, Cin = x.shape
@@ -483,7 +542,7 @@ def conv2d_backward(dOut, x, w, pad="zero", *, need_din=True, need_dw=True, stre
     ws = torch.empty(rise_conv2d_backward_workspace(B, Cin, Cout, H, W), device=x.device,
                      dtype=torch.uint8)
     rise_conv2d_backward(dIn, dW, dOut, x, w, B, Cin, Cout, H, W, kh=w.shape[2], kw=w.shape[3],
-                         pad=pad, ws=ws, stream=stream)
+                         pad=pad, ws=ws)
     return dIn, dW
 
 

@@ -20,8 +20,15 @@ class RiseGemmFn(torch.autograd.Function):
         from . import gemm_backward
 
         A, B = ctx.saved_tensors
-        dA, dB = gemm_backward(dC, A, B, mode=ctx.mode, need_dA=ctx.needs_input_grad[0],
+        # the backward products read FP32 operands; bfloat16 operands (mode "bf16")
+        # widen exactly, and each gradient is returned in its operand's type
+        dA, dB = gemm_backward(dC.float(), A.float(), B.float(), mode=ctx.mode,
+                               need_dA=ctx.needs_input_grad[0],
                                need_dB=ctx.needs_input_grad[1])
+        if dA is not None:
+            dA = dA.to(A.dtype)
+        if dB is not None:
+            dB = dB.to(B.dtype)
         return dA, dB, None
 
 

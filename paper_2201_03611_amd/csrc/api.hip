@@ -423,11 +423,22 @@ rise_status rise_gemm_backward(float* dA, int64_t ldda, float* dB, int64_t lddb,
     if (overlaps(span(dA, M, K, ldda, 4), span(dB, K, N, lddb, 4)))
       return fail(RISE_ERR_ALIAS, "rise_gemm_backward: dA overlaps dB");
   }
+  // Every output is checked against every input, not only against the inputs of
+  // its own product: dA is written before the dB product reads A, and the
+  // workspace is rewritten by each product's operand preparation.
   Range rc = span(dC, M, N, lddc, 4), ra = span(A, M, K, lda, 4), rb = span(B, K, N, ldb, 4);
-  if (dA && (overlaps(span(dA, M, K, ldda, 4), rc) || overlaps(span(dA, M, K, ldda, 4), rb)))
+  const Range rda = dA ? span(dA, M, K, ldda, 4) : Range{0, 0};
+  const Range rdb = dB ? span(dB, K, N, lddb, 4) : Range{0, 0};
+  if (overlaps(rda, rc) || overlaps(rda, ra) || overlaps(rda, rb))
     return fail(RISE_ERR_ALIAS, "rise_gemm_backward: dA overlaps an input");
-  if (dB && (overlaps(span(dB, K, N, lddb, 4), rc) || overlaps(span(dB, K, N, lddb, 4), ra)))
+  if (overlaps(rdb, rc) || overlaps(rdb, ra) || overlaps(rdb, rb))
     return fail(RISE_ERR_ALIAS, "rise_gemm_backward: dB overlaps an input");
+  if (ws && ws_bytes > 0) {
+    const Range rw{(uintptr_t)ws, (uintptr_t)ws + ws_bytes};
+    if (overlaps(rw, rda) || overlaps(rw, rdb) || overlaps(rw, rc) || overlaps(rw, ra) ||
+        overlaps(rw, rb))
+      return fail(RISE_ERR_ALIAS, "rise_gemm_backward: workspace overlaps an operand");
+  }
   rise_status st = RISE_OK;
   if (dA) {  // dA (M x K) = dC (M x N) . transpose(B), B stored K x N
     st = rise_gemm(dA, ldda, dC, RISE_F32, lddc, RISE_OP_N, B, RISE_F32, ldb, RISE_OP_T, M, K, N,
@@ -621,12 +632,9 @@ rise_status rise_plan_tile(const rise_plan* plan, int32_t problem, rise_tile* ti
   clear_error();
   if (!plan || !plan->impl || !tile) return fail(RISE_ERR_NULL, "rise_plan_tile: NULL");
   const int k = plan_kind(plan->impl, problem);
-  if (k < 0 || kind_is_stencil(k)) return fail(RISE_ERR_SHAPE, "rise_plan_tile: not a GEMM problem");
-  const char* n = kind_name(k);  // "<dtype>_<bm>x<bn>_<op>"
-  int bm = 0, bn = 0;
-  const char* us = strchr(n, '_');
-  if (!us || sscanf(us + 1, "%dx%d", &bm, &bn) != 2) return fail(RISE_ERR_HIP, "rise_plan_tile");
-  *tile = rise_tile{bm, bn, 32};
+  if (k < 0) return fail(RISE_ERR_SHAPE, "rise_plan_tile: problem index outside the plan");
+  if (kind_is_stencil(k)) return fail(RISE_ERR_SHAPE, "rise_plan_tile: not a GEMM problem");
+  *tile = kind_tile(k);
   return RISE_OK;
 }
 

@@ -22,5 +22,7 @@ int kind_is_stencil(int k);
 int kind_stencil_side(int k);
 int kind_dtype(int k);
 int kind_opb(int k);
+// (bm, bn, bk) a GEMM tile kind runs; all zero for stencil kinds
+rise_tile kind_tile(int k);
 
 }  // namespace rise

@@ -439,5 +439,9 @@ int kind_is_stencil(int k) { return k >= STENCIL_1; }
 int kind_stencil_side(int k) { return 1 + 2 * ((k - STENCIL_1) % 4); }
 int kind_dtype(int k) { return k >= BF16_64x64_N && k <= BF16_128x128_T ? RISE_BF16 : RISE_F32; }
 int kind_opb(int k) { return k < STENCIL_1 ? (k & 1) : -1; }
+rise_tile kind_tile(int k) {
+  if (k < 0 || k >= STENCIL_1) return rise_tile{0, 0, 0};
+  return rise_tile{kShape[k].bm, kShape[k].bn, kShape[k].bk};
+}
 
 }  // namespace rise

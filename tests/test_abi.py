@@ -274,6 +274,17 @@ def test_backward_rejections(lib):
               None) == 2
     assert GB(None, 0, None, 0, FAKE_C, 64, FAKE_A, 64, FAKE_B, 64, 64, 64, 64, 0, None, 0,
               None) == 0  # nothing requested
+    # dA overlapping A: dA is written before the dB product reads A
+    assert GB(FAKE_A + 256, 64, 0x60000000, 64, FAKE_C, 64, FAKE_A, 64, FAKE_B, 64, 64, 64, 64,
+              0, None, 0, None) == 3
+    # dB overlapping B
+    assert GB(0x60000000, 64, FAKE_B, 64, FAKE_C, 64, FAKE_A, 64, FAKE_B, 64, 64, 64, 64, 0,
+              None, 0, None) == 3
+    # workspace overlapping A (rewritten by the dA product's operand preparation)
+    need = lib.rise_gemm_backward_workspace(64, 64, 64, 2)
+    assert need > 0
+    assert GB(0x60000000, 64, 0x68000000, 64, FAKE_C, 64, FAKE_A, 64, FAKE_B, 64, 64, 64, 64, 2,
+              FAKE_A, need, None) == 3
     SB = lib.rise_stencil2d_backward
     need = lib.rise_stencil2d_backward_workspace(64, 64, 5, 5)
     assert need > 0

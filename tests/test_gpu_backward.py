@@ -150,3 +150,52 @@ def test_autograd_stencil(rise):
     sin, sw = oracle.stencil2d_backward(np.abs(G), img, np.abs(w), oracle.PAD_ZERO)
     assert componentwise(host(ti.grad), rin, sin) <= TOL
     assert componentwise(host(tw.grad), rw, sw) <= TOL
+
+
+def test_autograd_gemm_bf16_operands(rise):
+    # mode "bf16" with bfloat16 operands: the backward products take the exactly
+    # widened operands, round dC to bf16 as the mode does, and return gradients in
+    # the operands' type (the oracle evaluates the same mode on the same values)
+    import torch
+
+    g = ri.rng(9)
+    A = ri.uniform_matrix(g, 70, 48)
+    B = ri.uniform_matrix(g, 48, 40)
+    G = ri.uniform_matrix(g, 70, 40)
+    Ab = oracle.bf16_bits_to_f32(ri.bf16_bits_from_f32(A)).reshape(A.shape)
+    Bb = oracle.bf16_bits_to_f32(ri.bf16_bits_from_f32(B)).reshape(B.shape)
+    tA = dev(Ab).to(torch.bfloat16).requires_grad_(True)
+    tB = dev(Bb).to(torch.bfloat16).requires_grad_(True)
+    C = rise.RiseGemmFn.apply(tA, tB, "bf16")
+    C.backward(dev(G))
+    assert tA.grad.dtype == torch.bfloat16 and tB.grad.dtype == torch.bfloat16
+    refA = oracle.gemm_mode(G, np.ascontiguousarray(Bb.T), oracle.MODE_BF16)
+    refB = oracle.gemm_mode(np.ascontiguousarray(Ab.T), G, oracle.MODE_BF16)
+    # the gradient itself is rounded once to bf16 on return (relative 2^-8), on top of
+    # the mode's FP32-accumulated product of bf16-rounded operands
+    sA = oracle.gemm(np.abs(G), np.abs(Bb), opB=1)
+    sB = oracle.gemm(np.abs(Ab), np.abs(G), opA=1)
+    assert componentwise(host(tA.grad.float()), refA, sA) <= 2.0 ** -8 + TOL
+    assert componentwise(host(tB.grad.float()), refB, sB) <= 2.0 ** -8 + TOL
+
+
+def test_wrappers_on_a_side_stream(rise):
+    # a wrapper called with stream= allocates its output and workspace on that
+    # stream; the results equal the default-stream call bit for bit
+    import torch
+
+    g = ri.rng(10)
+    A = dev(ri.uniform_matrix(g, 300, 200))
+    B = dev(ri.uniform_matrix(g, 200, 260))
+    img = dev(ri.uniform_matrix(g, 100, 300, 0.0, 1.0))
+    w = dev(ri.gaussian_weights(5, 1.0))
+    ref_c = rise.gemm(A, B, mode="bf16x3")
+    ref_s = rise.stencil2d(img, w)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    for _ in range(3):
+        c = rise.gemm(A, B, mode="bf16x3", stream=s)
+        o = rise.stencil2d(img, w, stream=s)
+    s.synchronize()
+    assert torch.equal(c, ref_c) and torch.equal(o, ref_s)

@@ -119,23 +119,113 @@ def test_config_layer_crops(rise):
         check_out(got, ref[oy0:oy0 + oy1, ox0:ox0 + ox1], scale[oy0:oy0 + oy1, ox0:ox0 + ox1])
 
 
-def test_config_layer_backward_directional(rise):
-    # dW of the full layer: L(w) = <dOut, conv(x, w)> is linear in the (bf16-rounded)
-    # weights, so <dW, V> = <dOut, conv(x, V)> for a bf16-exact direction V
+def _taps(img, pad):
+    """The nine shifted views (dy, dx) of an NHWC batch under pad2D(1): element
+    [b, y, x, c] of view (dy, dx) is img[b, y + dy - 1, x + dx - 1, c], outside the
+    image 0 (zero) or the nearest edge pixel (clamp)."""
+    B, H, W, C = img.shape
+    p = np.pad(img, ((0, 0), (1, 1), (1, 1), (0, 0)), mode="edge" if pad == "clamp" else "constant")
+    return [p[:, dy:dy + H, dx:dx + W, :] for dy in range(3) for dx in range(3)]
+
+
+def dw_scale(g_abs, x_abs, pad):
+    """sum over (b, y, x) of |dOut| * |window| per (co, ci, dy, dx): the componentwise
+    scale of dW (a tolerance only; the expected values come from the oracle)."""
+    Cout, Cin = g_abs.shape[-1], x_abs.shape[-1]
+    G = g_abs.reshape(-1, Cout).astype(np.float64)
+    out = np.empty((Cout, Cin, 9))
+    for t, v in enumerate(_taps(x_abs, pad)):
+        out[:, :, t] = G.T @ v.reshape(-1, Cin).astype(np.float64)
+    return out.reshape(Cout, Cin, 3, 3)
+
+
+def din_scale(g_abs, w_abs):
+    """|dIn| scale under zero padding: sum over taps and co of |dOut| |w| at the
+    pixels whose window holds this one (the adjoint applied to absolute values)."""
+    B, H, W, Cout = g_abs.shape
+    Cin = w_abs.shape[1]
+    out = np.zeros((B, H, W, Cin))
+    gp = np.pad(g_abs.astype(np.float64), ((0, 0), (1, 1), (1, 1), (0, 0)))
+    for dy in range(3):
+        for dx in range(3):
+            # pixel (y, x) is tap (dy, dx) of output (y - dy + 1, x - dx + 1)
+            src = gp[:, 2 - dy:2 - dy + H, 2 - dx:2 - dx + W, :]
+            out += src @ w_abs[:, :, dy, dx].astype(np.float64)
+    return out
+
+
+def check_dw(got, ref, scale):
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    assert np.all(err <= 1e-5 * scale + 1e-30), float(np.max(err / (scale + 1e-30)))
+
+
+@pytest.mark.parametrize("pad", ["zero", "clamp"])
+def test_layer_backward_multi_tile(rise, pad):
+    # 8 x 200 x 129 (ragged in both dimensions) with 32 -> 32 channels: 2400 dW
+    # tiles over 512 persistent workgroups, so every workgroup walks a run of
+    # several tiles (with the next tile's loads in flight) before the fixed-order
+    # reduction of the partials; all of dW and (zero padding) all of dIn against
+    # the oracle.  dIn under clamp padding is refused by the library.
+    B, H, W, C = 8, 200, 129, 32
+    x, w, dout = ri.conv_inputs(B, C, C, H, W, seed=ri.SEED_CONV + 3, w_std=0.05)
+    pm = oracle.PAD_ZERO if pad == "zero" else oracle.PAD_CLAMP
+    print(f"conv bwd multi-tile pad={pad}", flush=True)
+    dIn, dW = rise.conv2d_backward(bf16_dev(dout), bf16_dev(x), dev(w), pad=pad,
+                                   need_din=pad == "zero")
+    xf = oracle.bf16_bits_to_f32(x).reshape(x.shape)
+    gf = oracle.bf16_bits_to_f32(dout).reshape(dout.shape)
+    rin, rw = oracle.conv2d_backward(gf, x, wq(w), pm, want_din=pad == "zero")
+    check_dw(host(dW), rw, dw_scale(np.abs(gf), np.abs(xf), pad))
+    if pad == "zero":
+        check_out(decode(dIn), rin, din_scale(np.abs(gf), np.abs(wq(w))))
+
+
+def test_layer_backward_clamp_din_refused(rise):
+    x, w, dout = case_inputs(1, 4, 8, 32, 32, 5)
+    with pytest.raises(rise.RiseError, match="zero padding"):
+        rise.conv2d_backward(bf16_dev(dout), bf16_dev(x), dev(w), pad="clamp")
+
+
+def test_config_layer_backward(rise):
+    # The layer's full size (batch 32, 64 -> 64 channels, 512 x 512), launched as
+    # the benchmark launches it.
+    #  * all of dW for image 0 (its own launch: 2048 tiles, four per persistent
+    #    workgroup) against the oracle, element by element;
+    #  * the batch's dW equals the sum of the 32 per-image dW (each a launch of
+    #    its own), within the FP32 accumulation bound of the summed scales;
+    #  * dIn of the batch launch on full-width bands of rows at the top, middle
+    #    and bottom of three images against the oracle on the same bands (with
+    #    their one-row halo of dOut).
     import torch
 
-    B, H, W, C = 8, 512, 512, 64
+    B, H, W, C = 32, 512, 512, 64
     x, w, dout = ri.conv_inputs(B, C, C, H, W, seed=ri.SEED_CONV + 1)
+    dx_, dg_ = bf16_dev(x), bf16_dev(dout)
     print("conv full-size backward", flush=True)
-    dIn, dW = rise.conv2d_backward(bf16_dev(dout), bf16_dev(x), dev(w))
-    V = wq((ri.rng(9).standard_normal((C, C, 3, 3)) * 0.05).astype(np.float32))
-    LV = decode(rise.conv2d(bf16_dev(x), dev(V))).astype(np.float64)
-    g = oracle.bf16_bits_to_f32(dout).reshape(dout.shape).astype(np.float64)
-    fd = float(np.sum(g * LV))
-    lin = float(np.sum(host(dW).astype(np.float64) * V))
-    scale = float(np.sum(np.abs(g) * np.abs(LV)))
-    assert abs(fd - lin) <= 2.0 ** -8 * scale, (fd, lin, scale)
-    assert np.all(np.isfinite(decode(dIn)))
+    dIn, dW = rise.conv2d_backward(dg_, dx_, dev(w))
+    dW = host(dW).astype(np.float64)
+    per = []
+    for b in range(B):
+        _, dWb = rise.conv2d_backward(dg_[b:b + 1], dx_[b:b + 1], dev(w), need_din=False)
+        per.append(host(dWb).astype(np.float64))
+    torch.cuda.synchronize()
+    xf = oracle.bf16_bits_to_f32(x).reshape(x.shape)
+    gf = oracle.bf16_bits_to_f32(dout).reshape(dout.shape)
+    scales = [dw_scale(np.abs(gf[b:b + 1]), np.abs(xf[b:b + 1]), "zero") for b in range(B)]
+    print("conv full-size backward: oracle dW of image 0", flush=True)
+    _, rw0 = oracle.conv2d_backward(gf[:1], x[:1], wq(w), oracle.PAD_ZERO, want_din=False)
+    check_dw(per[0], rw0, scales[0])
+    check_dw(dW, np.sum(per, axis=0), 2 * np.sum(scales, axis=0))
+    dIn_h = decode(dIn)
+    for b, y0 in [(0, 0), (13, 200), (31, 448)]:
+        ys, ye = max(y0 - 1, 0), min(y0 + 65, H)
+        rin, _ = oracle.conv2d_backward(gf[b:b + 1, ys:ye], x[b:b + 1, ys:ye], wq(w),
+                                        oracle.PAD_ZERO, want_dw=False)
+        sin = din_scale(np.abs(gf[b:b + 1, ys:ye]), np.abs(wq(w)))
+        # rows whose contributing dOut rows all lie in the band (or beyond an image edge)
+        lo = y0 - ys
+        hi = min(64, (ye - ys) - lo - (1 if ye < H else 0))
+        check_out(dIn_h[b, y0:y0 + hi], rin[0, lo:lo + hi], sin[0, lo:lo + hi])
 
 
 def test_autograd_layer(rise):

@@ -101,7 +101,9 @@ def test_gemv_equals_the_papers_mv_kernel(rise):
 
 @pytest.mark.parametrize("trans", [False, True])
 def test_gemv_16384_sampled(rise, trans):
-    # the benchmark size: 16384 x 16384 (1 GiB of A), sampled outputs
+    # the benchmark size and launch: 16384 x 16384 (1 GiB of A) drawn on the device
+    # as the benchmark draws it; 200 sampled outputs plus the ends against the
+    # oracle's MV (its GEMM with N = 1) on the same stored values
     import torch
 
     n = 16384
@@ -113,13 +115,25 @@ def test_gemv_16384_sampled(rise, trans):
     op = rise.RISE_OP_T if trans else rise.RISE_OP_N
     nws = rise.rise_gemv_workspace(n, n, op)
     ws = torch.empty(nws, device="cuda", dtype=torch.uint8) if nws else None
-    print(f"gemv {n} trans={trans}", flush=True)
+    print(f"gemv {n} trans={trans} parts={rise.rise_gemv_parts(n, n, op)}", flush=True)
     rise.rise_gemv(y, dA, dx, n, n, lda=n, opA=op, ws=ws)
-    rows = ri.sample_indices(ri.rng(5), n, 1, 200)[0]
-    xh = host(dx).astype(np.float64)
-    yh = host(y)
-    for r in rows:
-        a = host(dA[:, r] if trans else dA[r]).astype(np.float64)
-        ref = float(a @ xh)
-        scale = float(np.abs(a) @ np.abs(xh))
-        assert abs(yh[r] - ref) <= TOL * scale, (r, yh[r], ref)
+    rows = np.concatenate([ri.sample_indices(ri.rng(5), n, 1, 200)[0], [1, n - 2]])
+    zeros = np.zeros_like(rows)
+    Ah, xh, yh = host(dA), host(dx).reshape(n, 1), host(y)
+    ref = oracle.gemm_sampled(Ah, xh, rows, zeros, opA=int(trans))
+    scale = oracle.gemm_sampled(np.abs(Ah), np.abs(xh), rows, zeros, opA=int(trans))
+    assert componentwise(yh[rows], ref, scale) <= TOL
+
+
+@pytest.mark.parametrize("M,K", [(1000, 40000), (3000, 12001)])
+def test_gemv_transposed_wide_split(rise, M, K):
+    # grids of at least two workgroups per compute unit take the split-K kernel
+    # with two rows of loads in flight per thread (the 16384^2 launch runs it too)
+    parts = rise.rise_gemv_parts(M, K, rise.RISE_OP_T)
+    mblocks = (M + 1023) // 1024
+    assert mblocks * parts >= 2 * 256, (M, K, parts)
+    g = ri.rng(M + K)
+    A = ri.uniform_matrix(g, M, K)
+    x = ri.uniform_matrix(g, K, 1)
+    y = run(rise, np.ascontiguousarray(A.T), x, True)
+    assert componentwise(y[:, None], oracle.gemm(A, x), gemm_scale(A, x)) <= TOL

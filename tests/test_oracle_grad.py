@@ -107,3 +107,37 @@ def test_conv_gradients_library_and_fd():
     Gd = G.astype(np.float64)
     f_in = lambda X: float((Gd * oracle.conv2d(X, w, PAD_ZERO)).sum())
     np.testing.assert_allclose(din, fd_grad(f_in, x.astype(np.float64)), rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("kh,kw", [(3, 3), (5, 3)])
+def test_conv_gradients_clamp_padding(kh, kw):
+    # clamp (replicate) padding of the layer: torch float64 autograd through
+    # F.pad(mode="replicate") + F.conv2d, and central differences in both the
+    # input and the weights; the adjoint sends every out-of-range tap to the
+    # nearest edge pixel, so edge pixels collect several taps
+    g = ri.rng(61 + kh)
+    x = g.standard_normal(size=(2, 4, 6, 3)).astype(np.float32)
+    w = g.standard_normal(size=(2, 3, kh, kw)).astype(np.float32)
+    G = g.standard_normal(size=(2, 4, 6, 2)).astype(np.float32)
+    din, dw = oracle.conv2d_backward(G, x, w, PAD_CLAMP)
+    ry, rx = (kh - 1) // 2, (kw - 1) // 2
+    xt = torch.from_numpy(x).double().permute(0, 3, 1, 2).requires_grad_(True)
+    wt = torch.from_numpy(w).double().requires_grad_(True)
+    out = F.conv2d(F.pad(xt, (rx, rx, ry, ry), mode="replicate"), wt).permute(0, 2, 3, 1)
+    (out * torch.from_numpy(G).double()).sum().backward()
+    np.testing.assert_allclose(din, xt.grad.permute(0, 2, 3, 1).numpy(), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(dw, wt.grad.numpy(), rtol=1e-12, atol=1e-12)
+    Gd = G.astype(np.float64)
+    f_in = lambda X: float((Gd * oracle.conv2d(X, w, PAD_CLAMP)).sum())
+    np.testing.assert_allclose(din, fd_grad(f_in, x.astype(np.float64)), rtol=1e-11, atol=1e-11)
+    # the layer is linear in w: <dW, V> = <G, conv(x, V)> for any V (the oracle takes
+    # f32 weights, so the identity replaces differences of perturbed weights)
+    V = g.standard_normal(size=w.shape).astype(np.float32)
+    lhs = float(np.sum(dw * V.astype(np.float64)))
+    rhs = float((Gd * oracle.conv2d(x, V, PAD_CLAMP)).sum())
+    assert abs(lhs - rhs) <= 1e-11 * max(1.0, abs(rhs))
+    # clamping maps taps only onto the first/last row and column: there the
+    # gradient differs from zero padding's, everywhere else it is the same
+    din0, _ = oracle.conv2d_backward(G, x, w, PAD_ZERO)
+    assert not np.allclose(din[:, 0, 0], din0[:, 0, 0])
+    np.testing.assert_allclose(din[:, 1:-1, 1:-1], din0[:, 1:-1, 1:-1], rtol=1e-12, atol=1e-12)

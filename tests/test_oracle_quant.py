@@ -140,6 +140,23 @@ def test_gemm_mode_definitions():
     Bh, Bl = [oracle.bf16_bits_to_f32(p).astype(np.float64) for p in oracle.split_bf16(B)]
     np.testing.assert_allclose(oracle.gemm_mode(A, B, oracle.MODE_BF16X3),
                                Ah @ Bh + Ah @ Bl + Al @ Bh, rtol=1e-13, atol=1e-13)
+    # BF16X6: exactly the six products A_i B_j with i + j <= 4 of the three-way
+    # splits -- neither fewer nor more (A2 B3, A3 B2 and A3 B3 are left out)
+    A1, A2, A3 = [oracle.bf16_bits_to_f32(p).astype(np.float64).reshape(A.shape)
+                  for p in oracle.split3_bf16(A)]
+    B1, B2, B3 = [oracle.bf16_bits_to_f32(p).astype(np.float64).reshape(B.shape)
+                  for p in oracle.split3_bf16(B)]
+    six = A1 @ B1 + A1 @ B2 + A2 @ B1 + A1 @ B3 + A2 @ B2 + A3 @ B1
+    x6 = oracle.gemm_mode(A, B, oracle.MODE_BF16X6)
+    sc = np.abs(Ad) @ np.abs(Bd)
+    # each left-out product reaches well above 1e-14 of the scale somewhere, so a
+    # seventh product would show; the comparisons allow only fp64 reordering
+    for P in (A2 @ B3, A3 @ B2, A3 @ B3):
+        assert np.max(np.abs(P) / sc) > 1e-12
+    dropped = A2 @ B3 + A3 @ B2 + A3 @ B3
+    assert np.max(np.abs(x6 - six) / sc) < 1e-14
+    full = (A1 + A2 + A3) @ (B1 + B2 + B3)
+    assert np.max(np.abs(x6 + dropped - full) / sc) < 1e-14
     qa, sa = oracle.quant_e4m3_rows(A)
     qb, sb = oracle.quant_e4m3_cols(B)
     dec = np.vectorize(oracle.e4m3_decode)
