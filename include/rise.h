@@ -72,8 +72,9 @@ typedef enum { RISE_PAD_CLAMP = 0, RISE_PAD_ZERO = 1 } rise_pad;
 /* An explicit schedule for one GEMM: the tile sizes produced by splitJoinMap
  * on the two maps (bm, bn) and by split on the reduction (bk).  The paper keeps
  * such choices outside the program, supplied by a strategy (Sec. IV-B/C); here
- * the caller passes one or NULL, and NULL takes the library's default for the
- * mode.  rise_gemm_tiles() lists the supported ones. */
+ * the caller passes one or NULL, and NULL takes the tune cache's choice for
+ * these sizes and mode (rise_autotune_gemm below) or, without one, the
+ * library's default for the mode.  rise_gemm_tiles() lists the supported ones. */
 typedef struct {
   int32_t bm, bn, bk;
 } rise_tile;
@@ -88,11 +89,12 @@ const char* rise_last_error(void);
 int32_t rise_gemm_tiles(rise_mode mode, rise_tile* out, int32_t cap);
 
 /* The strategy rise_gemm applies when its `tile` argument is NULL: writes to
- * *out the tile the library picks for these sizes and mode (Sec. IV-B/C leave
- * that choice to a strategy outside the program; this reports it).  Host-only,
- * enqueues nothing.  Errors: sizes outside [0, 2^31) (RISE_ERR_SHAPE), an
- * unknown mode (RISE_ERR_UNSUPPORTED), out NULL (RISE_ERR_NULL); *out is then
- * left unchanged. */
+ * *out the tile the library picks for these sizes and mode -- the tune cache's
+ * entry for them on the current device if there is one, else the built-in
+ * default (Sec. IV-B/C leave that choice to a strategy outside the program;
+ * this reports it).  Host-only, enqueues nothing.  Errors: sizes outside
+ * [0, 2^31) (RISE_ERR_SHAPE), an unknown mode (RISE_ERR_UNSUPPORTED), out NULL
+ * (RISE_ERR_NULL); *out is then left unchanged. */
 rise_status rise_gemm_default_tile(int64_t M, int64_t N, int64_t K, rise_mode mode,
                                    rise_tile* out);
 
@@ -101,7 +103,8 @@ rise_status rise_gemm_default_tile(int64_t M, int64_t N, int64_t K, rise_mode mo
 /* ------------------------------------------------------------------------ */
 
 /* Bytes of workspace rise_gemm needs for these sizes, mode and tile (NULL =
- * default tile).  0 for RISE_MODE_F32, which reads its operands in place. */
+ * the tile rise_gemm_default_tile reports).  0 for RISE_MODE_F32, which reads
+ * its operands in place. */
 size_t rise_gemm_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode,
                            const rise_tile* tile);
 
@@ -242,7 +245,8 @@ typedef struct {
 int32_t rise_stencil_schedules(rise_stencil_schedule* out, int32_t cap);
 
 /* The schedule rise_stencil2d runs when its `sched` argument is NULL, written
- * to *out (a strategy's choice, Sec. IV-B/C, reported).  Windows other than
+ * to *out (a strategy's choice, Sec. IV-B/C, reported): the tune cache's entry
+ * for (H, W, k) on the current device if there is one, else the default.  Windows other than
  * square 1, 3, 5 and 7 run the direct per-output kernel, reported as
  * variant -1, rows 0.  Host-only, enqueues nothing.  Errors: sizes outside
  * [0, 2^31) (RISE_ERR_SHAPE), even or oversized window sides
@@ -345,6 +349,45 @@ rise_status rise_conv2d_backward(uint16_t* dIn, float* dW, const uint16_t* dOut,
                                  const uint16_t* in, const float* w, int32_t B, int32_t Cin,
                                  int32_t Cout, int32_t H, int32_t W, int32_t kh, int32_t kw,
                                  rise_pad pad, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuning: the strategy search (Sec. IV-B/C keep tile sizes and the      */
+/* mapping of maps onto the hardware outside the program, as an explicit    */
+/* strategy that a user or a search supplies)                               */
+/* ------------------------------------------------------------------------ */
+
+/* Time every supported tile of `mode` (rise_gemm_tiles) on an M x N x K product
+ * of row-major FP32 operands (opA = opB = RISE_OP_N) on the current device and
+ * record the fastest in the text cache file `cache_path`, keyed by (M, N, K,
+ * mode, GPU architecture name such as "gfx950"); an entry of the same key is
+ * replaced, other entries are kept.  Allocates (and frees) device memory for
+ * the operands and the workspace and synchronises `stream`: not for the hot
+ * path.  Errors: cache_path NULL (RISE_ERR_NULL), sizes outside [1, 2^31) or
+ * operands above 16 GiB (RISE_ERR_SHAPE), an unknown mode or an unwritable
+ * file (RISE_ERR_UNSUPPORTED), no device or a HIP failure (RISE_ERR_HIP). */
+rise_status rise_autotune_gemm(const char* cache_path, int64_t M, int64_t N, int64_t K,
+                               rise_mode mode, void* stream);
+
+/* The same for the stencil: times every schedule of rise_stencil_schedules()
+ * on an H x W FP32 image with a k x k window (k in {1, 3, 5, 7}, clamp
+ * padding) and records the fastest under (H, W, k, architecture).  Errors as
+ * for rise_autotune_gemm (another k: RISE_ERR_UNSUPPORTED). */
+rise_status rise_autotune_stencil(const char* cache_path, int64_t H, int64_t W, int32_t k,
+                                  void* stream);
+
+/* The cache file that tile = NULL / sched = NULL consult (rise_gemm,
+ * rise_gemm_workspace, rise_gemm_default_tile, rise_gemm_backward,
+ * rise_stencil2d, rise_stencil2d_default_schedule).  The file is read now and
+ * again after each autotune call that writes it; NULL or "" disables the
+ * cache.  Until this is called the library uses the file named by the
+ * RISE_TUNE_CACHE environment variable, if set.  A missing file is an empty
+ * cache.  Process-wide; the file format is one line per entry:
+ *   gemm <arch> <M> <N> <K> <mode> <bm> <bn> <bk> <microseconds>
+ *   stencil <arch> <H> <W> <k> <variant> <rows> <microseconds>
+ * Changing the cache between a workspace query and the call can change the
+ * tile and so the workspace needed; rise_gemm then fails with
+ * RISE_ERR_WORKSPACE rather than overrun. */
+rise_status rise_set_tune_cache(const char* path);
 
 /* ------------------------------------------------------------------------ */
 /* Batched form: many problems, one persistent launch                        */

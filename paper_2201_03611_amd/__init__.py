@@ -340,6 +340,23 @@ def rise_autotune_batched(table_path, stream=None):
            "rise_autotune_batched")
 
 
+def rise_autotune_gemm(cache_path, M, N, K, mode="f32", stream=None):
+    """Time every tile of `mode` at M x N x K and record the fastest in cache_path."""
+    _check(lib.rise_autotune_gemm(cache_path.encode(), M, N, K, _mode(mode), _stream(stream)),
+           "rise_autotune_gemm")
+
+
+def rise_autotune_stencil(cache_path, H, W, k, stream=None):
+    """Time every stencil schedule at H x W, k x k and record the fastest in cache_path."""
+    _check(lib.rise_autotune_stencil(cache_path.encode(), H, W, k, _stream(stream)),
+           "rise_autotune_stencil")
+
+
+def rise_set_tune_cache(path):
+    """The cache file that tile=None / schedule=None consult (None disables it)."""
+    _check(lib.rise_set_tune_cache(path.encode() if path else None), "rise_set_tune_cache")
+
+
 class Plan:
     """Owning wrapper of a rise_plan (problem arrays are kept alive with it)."""
 

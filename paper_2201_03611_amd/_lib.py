@@ -96,6 +96,9 @@ SIGNATURES = {
     "rise_gemm_batched": (_INT, [ctypes.POINTER(RiseGemmProblem), _I32, _P]),
     "rise_stencil2d_batched": (_INT, [ctypes.POINTER(RiseStencilProblem), _I32, _P]),
     "rise_autotune_batched": (_INT, [ctypes.c_char_p, _P]),
+    "rise_autotune_gemm": (_INT, [ctypes.c_char_p, _I64, _I64, _I64, _INT, _P]),
+    "rise_autotune_stencil": (_INT, [ctypes.c_char_p, _I64, _I64, _I32, _P]),
+    "rise_set_tune_cache": (_INT, [ctypes.c_char_p]),
     "rise_stencil2d_backward_workspace": (_SZ, [_I64, _I64, _I32, _I32]),
     "rise_stencil2d_backward": (_INT, [_P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64, _P, _I32,
                                        _I32, _INT, _P, _SZ, _P]),

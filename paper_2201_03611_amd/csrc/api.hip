@@ -12,6 +12,7 @@
 #include "batched.h"
 #include "conv.h"
 #include "gemm_lowp.h"
+#include "tune.h"
 
 namespace rise {
 
@@ -69,6 +70,26 @@ bool overlaps(Range a, Range b) {
 
 bool dim_ok(int64_t v) { return v >= 0 && v < kDimLimit; }
 
+// The tile a GEMM runs when the caller passes none: the tune cache's entry for
+// these sizes and mode on this device, else the built-in default of the mode.
+rise_tile chosen_gemm_tile(int64_t M, int64_t N, int64_t K, rise_mode mode) {
+  rise_tile t;
+  if (M > 0 && N > 0 && K > 0 && tune_lookup_gemm(M, N, K, (int)mode, &t) &&
+      (mode == RISE_MODE_F32 ? gemm_f32_tile_supported(t) : gemm_lowp_tile_supported(mode, t)))
+    return t;
+  return mode == RISE_MODE_F32 ? gemm_f32_default_tile((int)M, (int)N, (int)K)
+                               : gemm_lowp_default_tile(mode, (int)M, (int)N, (int)K);
+}
+
+// The schedule a stencil runs when the caller passes none (tune cache, else default).
+rise_stencil_schedule chosen_stencil_schedule(int64_t H, int64_t W, int kh, int kw) {
+  rise_stencil_schedule sc;
+  if (kh == kw && H > 0 && W > 0 && tune_lookup_stencil(H, W, kh, &sc) &&
+      stencil_schedule_supported(sc))
+    return sc;
+  return stencil_default_schedule((int)H, (int)W, kh, kw);
+}
+
 }  // namespace
 }  // namespace rise
 
@@ -105,8 +126,7 @@ rise_status rise_gemm_default_tile(int64_t M, int64_t N, int64_t K, rise_mode mo
   if (mode < RISE_MODE_F32 || mode > RISE_MODE_FP8)
     return fail(RISE_ERR_UNSUPPORTED, "rise_gemm_default_tile: unknown mode");
   if (!out) return fail(RISE_ERR_NULL, "rise_gemm_default_tile: out is NULL");
-  *out = mode == RISE_MODE_F32 ? gemm_f32_default_tile((int)M, (int)N, (int)K)
-                               : gemm_lowp_default_tile(mode, (int)M, (int)N, (int)K);
+  *out = chosen_gemm_tile(M, N, K, mode);
   return RISE_OK;
 }
 
@@ -114,7 +134,7 @@ size_t rise_gemm_workspace(int64_t M, int64_t N, int64_t K, rise_mode mode,
                            const rise_tile* tile) {
   if (mode == RISE_MODE_F32) return 0;
   if (!dim_ok(M) || !dim_ok(N) || !dim_ok(K)) return 0;
-  rise_tile t = tile ? *tile : gemm_lowp_default_tile(mode, (int)M, (int)N, (int)K);
+  rise_tile t = tile ? *tile : chosen_gemm_tile(M, N, K, mode);
   return gemm_lowp_workspace((int)M, (int)N, (int)K, mode, t);
 }
 
@@ -150,7 +170,7 @@ rise_status rise_gemm(float* C, int64_t ldc, const void* A, rise_dtype tA, int64
   if (mode == RISE_MODE_F32) {
     if (tA != RISE_F32 || tB != RISE_F32)
       return fail(RISE_ERR_DTYPE, "rise_gemm: mode F32 needs FP32 operands");
-    rise_tile t = tile ? *tile : gemm_f32_default_tile((int)M, (int)N, (int)K);
+    rise_tile t = tile ? *tile : chosen_gemm_tile(M, N, K, mode);
     if (!gemm_f32_tile_supported(t))
       return fail(RISE_ERR_UNSUPPORTED, "rise_gemm: tile not supported for mode F32");
     GemmF32Args a{C, ldc, (const float*)A, lda, (const float*)B, ldb, (int)M, (int)N, (int)K,
@@ -160,7 +180,7 @@ rise_status rise_gemm(float* C, int64_t ldc, const void* A, rise_dtype tA, int64
 
   if (mode != RISE_MODE_BF16 && (tA != RISE_F32 || tB != RISE_F32))
     return fail(RISE_ERR_DTYPE, "rise_gemm: split and FP8 modes need FP32 operands");
-  rise_tile t = tile ? *tile : gemm_lowp_default_tile(mode, (int)M, (int)N, (int)K);
+  rise_tile t = tile ? *tile : chosen_gemm_tile(M, N, K, mode);
   if (!gemm_lowp_tile_supported(mode, t))
     return fail(RISE_ERR_UNSUPPORTED, "rise_gemm: tile not supported for this mode");
   size_t need = gemm_lowp_workspace((int)M, (int)N, (int)K, mode, t);
@@ -225,8 +245,7 @@ rise_status rise_stencil2d_default_schedule(int64_t H, int64_t W, int32_t kh, in
                 "rise_stencil2d_default_schedule: window sides must be odd and <= 15");
   if (!out) return fail(RISE_ERR_NULL, "rise_stencil2d_default_schedule: out is NULL");
   const bool scheduled = kh == kw && (kh == 1 || kh == 3 || kh == 5 || kh == 7);
-  *out = scheduled ? stencil_default_schedule((int)H, (int)W, kh, kw)
-                   : rise_stencil_schedule{-1, 0};
+  *out = scheduled ? chosen_stencil_schedule(H, W, kh, kw) : rise_stencil_schedule{-1, 0};
   return RISE_OK;
 }
 
@@ -246,7 +265,7 @@ rise_status rise_stencil2d(float* out, int64_t ld_out, const float* in, int64_t 
   Range ro = span(out, H, W, ld_out, 4);
   if (overlaps(ro, span(in, H, W, ld_in, 4)) || overlaps(ro, span(w, kh, kw, kw, 4)))
     return fail(RISE_ERR_ALIAS, "rise_stencil2d: out overlaps in or w");
-  rise_stencil_schedule sc = sched ? *sched : stencil_default_schedule((int)H, (int)W, kh, kw);
+  rise_stencil_schedule sc = sched ? *sched : chosen_stencil_schedule(H, W, kh, kw);
   if (!stencil_schedule_supported(sc))
     return fail(RISE_ERR_UNSUPPORTED, "rise_stencil2d: unknown schedule");
   StencilArgs a{out, ld_out, in, ld_in, (int)H, (int)W, w, kh, kw, (int)pad};

@@ -328,3 +328,36 @@ def test_batched_rejections(lib):
     assert lib.rise_plan_create(None, None, 0, None, 0, None, None) == 1
     assert lib.rise_plan_launch(None, None) == 1
     assert lib.rise_plan_destroy(None) == 0
+
+
+def test_autotune_rejections(lib, tmp_path):
+    # validation happens before any device work (no GPU here)
+    path = str(tmp_path / "tune.txt").encode()
+    assert lib.rise_autotune_gemm(None, 64, 64, 64, 0, None) == 1
+    assert lib.rise_autotune_gemm(path, 0, 64, 64, 0, None) == 2
+    assert lib.rise_autotune_gemm(path, 64, 64, 1 << 31, 0, None) == 2
+    assert lib.rise_autotune_gemm(path, 64, 64, 64, 9, None) == 5
+    assert lib.rise_autotune_gemm(path, 1 << 20, 1 << 20, 1 << 20, 0, None) == 2  # > 16 GiB
+    assert lib.rise_autotune_stencil(None, 64, 64, 5, None) == 1
+    assert lib.rise_autotune_stencil(path, -1, 64, 5, None) == 2
+    assert lib.rise_autotune_stencil(path, 64, 64, 9, None) == 5
+    assert not os.path.exists(path)
+
+
+def test_tune_cache_without_entries_keeps_the_defaults(lib, tmp_path):
+    # an empty or unrelated cache leaves the built-in choices (which host-only
+    # queries report without a device)
+    from paper_2201_03611_amd._lib import RiseStencilSchedule, RiseTile
+
+    p = tmp_path / "tune.txt"
+    p.write_text("garbage line\nstencil gfx000 10 10 5 1 8 1.0\n")
+    before = RiseTile()
+    assert lib.rise_set_tune_cache(None) == 0
+    assert lib.rise_gemm_default_tile(4096, 4096, 4096, 0, ctypes.byref(before)) == 0
+    assert lib.rise_set_tune_cache(str(p).encode()) == 0
+    t = RiseTile()
+    assert lib.rise_gemm_default_tile(4096, 4096, 4096, 0, ctypes.byref(t)) == 0
+    assert (t.bm, t.bn, t.bk) == (before.bm, before.bn, before.bk)
+    sc = RiseStencilSchedule()
+    assert lib.rise_stencil2d_default_schedule(4096, 4096, 5, 5, ctypes.byref(sc)) == 0
+    assert lib.rise_set_tune_cache(None) == 0
