@@ -197,6 +197,12 @@ def main():
     result["strategy"] = {"gemm": f"f32 tile {gt[0]}x{gt[1]}x{gt[2]}",
                           "stencil": f"{sv} halo tile, {srows} output rows x 256 columns"}
 
+    # measured ceilings of this GPU beside the spec peaks
+    ceil = ceilings_leg(rise, torch, dev, stream)
+    result["ceilings"] = ceil
+    result["roofline"]["frac_measured_ceiling"] = round(gemm_tf / ceil["mfma_f32_tflops"], 4)
+    result["roofline_stencil"]["frac_measured_ceiling"] = round(sten_gbs / ceil["hbm_copy_gbps"], 4)
+
     # the stencil's events above start when the GEMM ends, so they include the
     # dispatch gap after it; the same launches back to back (rotating buffers)
     # give the kernel's own rate beside it
@@ -205,7 +211,10 @@ def main():
         for j in range(nsets)], 5) / nsets
     result["roofline_stencil"]["ms_back_to_back"] = round(ms_b2b, 5)
     result["roofline_stencil"]["achieved_back_to_back"] = round(bytes_sten / (ms_b2b * 1e-3) / 1e9, 1)
+    result["roofline_stencil"]["frac_back_to_back"] = round(
+        bytes_sten / (ms_b2b * 1e-3) / 1e9 / PEAK_HBM, 4)
 
+    result["gemm_backward"] = gemm_backward_leg(rise, ri, torch, dev, stream, result["ceilings"])
     if not args.no_precision:
         result["precision"] = precision_leg(rise, ri, np, torch, dev, stream)
     if not args.no_extra:
@@ -345,6 +354,61 @@ def event_ms(torch, stream, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def ceilings_leg(rise, torch, dev, stream):
+    """What this GPU reaches outside the patterns: a 2 GiB streaming device copy
+    (read + write bytes / time) and back-to-back matrix instructions on every
+    SIMD for FP32, BF16 and FP8 (rise_ceiling_*)."""
+    n = 1 << 29  # floats: 2 GiB per buffer
+    src = torch.empty(n, device=dev, dtype=torch.float32).fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = event_ms(torch, stream, lambda: rise.rise_ceiling_copy(dst, src, stream=stream), 5)
+    out = {"hbm_copy_gbps": round(2.0 * 4 * n / (ms * 1e-3) / 1e9, 1),
+           "hbm_copy_bytes": 2 * 4 * n}
+    del src, dst
+    torch.cuda.empty_cache()
+    sink = torch.empty(rise.rise_ceiling_mfma_sink_floats(), device=dev, dtype=torch.float32)
+    for mode, iters in (("f32", 4096), ("bf16", 4096), ("fp8", 4096)):
+        fl = rise.rise_ceiling_mfma(mode, iters, sink, stream=stream)
+        ms = event_ms(torch, stream, lambda: rise.rise_ceiling_mfma(mode, iters, sink,
+                                                                    stream=stream), 5)
+        out[f"mfma_{mode}_tflops"] = round(fl / (ms * 1e-3) / 1e12, 1)
+    out["spec"] = {"hbm_gbps": PEAK_HBM, "mfma_f32_tflops": PEAK_FP32_MFMA,
+                   "mfma_bf16_tflops": PEAK_BF16, "mfma_fp8_tflops": PEAK_FP8}
+    return out
+
+
+def gemm_backward_leg(rise, ri, torch, dev, stream, ceil):
+    """GEMM 4096^3 backward (dA = dC B^T, dB = A^T dC; A, B, dC ~ U(-1,1)): each
+    product timed on its own (the transposed-operand instantiations of the FP32
+    kernel), algorithmic 2 M N K flops each."""
+    n = 4096
+    A, B = ri.gemm_uniform(n, n, n, ri.SEED_GEMM_BWD)
+    G = ri.uniform_matrix(ri.rng(ri.SEED_GEMM_BWD + 1), n, n)
+    dA_, dB_, dG = (torch.from_numpy(x).to(dev) for x in (A, B, G))
+    gA = torch.empty_like(dA_)
+    gB = torch.empty_like(dB_)
+    fl = 2.0 * n ** 3
+    res = {}
+    for name, call in (
+            ("dA", lambda: rise.rise_gemm_backward(gA, None, dG, dA_, dB_, n, n, n, ldda=n,
+                                                   lddb=n, lddc=n, lda=n, ldb=n, stream=stream)),
+            ("dB", lambda: rise.rise_gemm_backward(None, gB, dG, dA_, dB_, n, n, n, ldda=n,
+                                                   lddb=n, lddc=n, lda=n, ldb=n, stream=stream))):
+        ms = event_ms(torch, stream, call, 10)
+        tf = fl / (ms * 1e-3) / 1e12
+        res[name] = {"ms": round(ms, 4), "tflops": round(tf, 2),
+                     "frac_mfma_peak": round(tf / PEAK_FP32_MFMA, 4),
+                     "frac_measured_ceiling": round(tf / ceil["mfma_f32_tflops"], 4)}
+    t = rise.rise_gemm_default_tile(n, n, n, "f32")
+    res["dA"]["strategy"] = f"f32 tile {t[0]}x{t[1]}x{t[2]}, B read through transpose"
+    res["dB"]["strategy"] = f"f32 tile {t[0]}x{t[1]}x{t[2]}, A read through transpose"
+    tot = res["dA"]["ms"] + res["dB"]["ms"]
+    res["both"] = {"ms": round(tot, 4), "tflops": round(2 * fl / (tot * 1e-3) / 1e12, 2)}
+    del dA_, dB_, dG, gA, gB
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_leg(rise, ri, torch, dev, stream):
     """512 GEMMs + 256 stencils: one graph launch of the persistent kernel, the same
     kernel without the graph, and 768 separate one-problem launches; lower bounds
@@ -431,9 +495,12 @@ def gemv_leg(rise, torch, dev, stream):
 
 def stencil_iterate_leg(rise, ri, torch, dev, stream):
     """16 steps of the 4096^2 5x5 Gaussian clamp stencil (iterate, Sec. VI): one
-    launch per step through the HBM double buffer, and 4 steps per launch in the
-    LDS double buffer.  Pixel-steps per second; the fused schedule against the
-    FP32 vector peak (k*k FMAs per pixel-step), the per-step one against HBM."""
+    launch per step through the double buffer of two images, and 4 steps per
+    launch in the LDS double buffer.  Pixel-steps per second; the fused schedule
+    against the FP32 vector peak (k*k FMAs per pixel-step).  The per-step
+    schedule's working set (input, two 64 MiB intermediates, output) fits the
+    256 MB last-level cache, which serves most of its reads: its bytes per
+    second are an equivalent rate, not an HBM fraction."""
     steps = 16
     img = torch.from_numpy(ri.image_uniform(H, W, 1003)).to(dev)
     w = torch.from_numpy(ri.gaussian_weights(KS, 1.0)).to(dev)
@@ -453,7 +520,7 @@ def stencil_iterate_leg(rise, ri, torch, dev, stream):
                      "strategy": f"{fuse} step(s) per launch, {-(-steps // fuse)} launches"}
     res["default_fuse"] = rise.rise_stencil2d_iterate_default_fuse(KS, KS)
     res["fused4"]["frac_fp32_vector_peak"] = round(res["fused4"]["tflops"] / PEAK_F32_VEC, 3)
-    res["per_step"]["frac_hbm_peak"] = round(res["per_step"]["hbm_gbps_equiv"] / PEAK_HBM, 3)
+    res["per_step"]["note"] = "reads served largely by the last-level cache; not an HBM figure"
     res["speedup_fused"] = round(res["per_step"]["ms"] / res["fused4"]["ms"], 2)
     return res
 
@@ -461,24 +528,27 @@ def stencil_iterate_leg(rise, ri, torch, dev, stream):
 def iterate_leg(rise, torch, dev, stream):
     """iterate with the tree-reduction body (binary tree, n = 2) over 2^26 FP32
     values (256 MiB, read once) to one sum, and over 4096 rows of 2^14 values
-    to 4096 sums: HBM GB/s of the input read against the 8 TB/s peak."""
+    to 4096 sums: HBM GB/s of the input read against the 8 TB/s peak.  The
+    launches rotate over three inputs (768 MiB, above the 256 MB last-level
+    cache), so every launch reads its input from HBM."""
     res = {}
     for name, n, m, k in (("tree_2pow26_to_1", 2, 1, 26), ("rows_4096x2pow14", 2, 4096, 14)):
         total = m * n ** k
         g = torch.Generator(device=dev)
         g.manual_seed(1300)
-        x = torch.rand((total,), device=dev, generator=g) * 2 - 1
+        xs = [torch.rand((total,), device=dev, generator=g) * 2 - 1 for _ in range(3)]
         out = torch.empty(m, device=dev)
         need = rise.rise_iterate_sum_workspace(n, m, k)
         ws = torch.empty(max(need, 1), device=dev, dtype=torch.uint8)
-        ms = event_ms(torch, stream, lambda: rise.rise_iterate_sum(out, x, n, m, k, ws=ws,
-                                                                   stream=stream), 20)
+        ms = event_ms(torch, stream, lambda: [rise.rise_iterate_sum(out, x, n, m, k, ws=ws,
+                                                                    stream=stream)
+                                              for x in xs], 7) / len(xs)
         gbs = 4.0 * (total + m) / (ms * 1e-3) / 1e9
         rounds = rise.rise_iterate_sum_passes(n, m, k)
         res[name] = {"us": round(ms * 1e3, 1), "gbps": round(gbs, 1),
                      "frac_hbm_peak": round(gbs / PEAK_HBM, 3),
                      "strategy": f"{len(rounds)} pass(es), rounds per pass {rounds}"}
-        del x
+        del xs
     torch.cuda.empty_cache()
     return res
 
@@ -558,12 +628,25 @@ def precision_leg(rise, ri, np, torch, dev, stream):
         big = np.abs(exact) >= 1e-3 * np.max(np.abs(exact))
         tf = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
         tl = rise.rise_gemm_default_tile(n, n, n, mode)
+        ms_prep = None
+        if mode != "f32":
+            # the operand preparation alone (A as rows of K, B read as columns), so
+            # the contraction's own rate can be read beside the end-to-end one
+            pa = torch.empty(rise.rise_prep_bytes(n, n, mode), device=dev, dtype=torch.uint8)
+            pb = torch.empty_like(pa)
+            ms_prep = event_ms(torch, stream, lambda: (
+                rise.rise_prep_operand(pa, n, n, dA, n, n, n, 1, mode, stream=stream),
+                rise.rise_prep_operand(pb, n, n, dB, n, n, 1, n, mode, stream=stream)), 5)
+            del pa, pb
         out[mode] = {"ms": round(ms, 3), "tflops_useful": round(tf, 1),
                      "strategy": f"{mode} tile {tl[0]}x{tl[1]}x{tl[2]}",
                      "frac_of_own_peak": round(tf / peaks[mode], 4),
                      "err_componentwise_max": err,
                      "err_normwise": float(np.max(diff) / np.max(np.abs(exact))),
                      "err_elementwise_floored_max": float(np.max(diff[big] / np.abs(exact[big])))}
+        if ms_prep is not None:
+            out[mode]["ms_prep"] = round(ms_prep, 3)
+            out[mode]["tflops_contraction"] = round(2.0 * n ** 3 / ((ms - ms_prep) * 1e-3) / 1e12, 1)
         del ws
     for mode in ["bf16", "bf16x3", "bf16x6", "fp8"]:
         out[mode]["err_ratio_to_f32"] = round(out[mode]["err_componentwise_max"] /

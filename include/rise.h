@@ -390,6 +390,30 @@ rise_status rise_autotune_stencil(const char* cache_path, int64_t H, int64_t W, 
 rise_status rise_set_tune_cache(const char* path);
 
 /* ------------------------------------------------------------------------ */
+/* Measured ceilings (the denominators of the roofline fractions beside the  */
+/* spec-sheet peaks; they compute nothing of the patterns)                   */
+/* ------------------------------------------------------------------------ */
+
+/* A streaming device copy of `bytes` (a multiple of 16; 16-byte aligned,
+ * non-overlapping device buffers): 16-byte loads, non-temporal 16-byte
+ * stores.  Timed over >= 2 GiB it gives the HBM bandwidth a kernel can reach
+ * (read + write bytes / time). */
+rise_status rise_ceiling_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Back-to-back matrix instructions on every SIMD (four waves per SIMD, four
+ * independent accumulators per wave), `iters` rounds: mode RISE_MODE_F32 runs
+ * v_mfma_f32_32x32x2_f32, RISE_MODE_BF16 v_mfma_f32_32x32x16_bf16, RISE_MODE_FP8
+ * the scaled v_mfma_scale_f32_32x32x64_f8f6f4.  *flops receives the flops the
+ * launch issues (host value, set before the call returns); timing the launch
+ * gives the matrix-core rate.  sink: device floats, at least
+ * rise_ceiling_mfma_sink_floats() of them (one value per lane is written so
+ * the loop is not removed).  Errors: NULL pointers, iters outside [1, 2^32],
+ * a short sink, another mode. */
+size_t rise_ceiling_mfma_sink_floats(void);
+rise_status rise_ceiling_mfma(rise_mode mode, int64_t iters, float* sink, size_t sink_floats,
+                              double* flops, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batched form: many problems, one persistent launch                        */
 /* ------------------------------------------------------------------------ */
 

@@ -357,6 +357,30 @@ def rise_set_tune_cache(path):
     _check(lib.rise_set_tune_cache(path.encode() if path else None), "rise_set_tune_cache")
 
 
+def rise_ceiling_copy(dst, src, stream=None):
+    """Streaming copy of src into dst (device tensors of equal byte size)."""
+    _require_cuda(dst, src)
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < n:
+        raise ValueError("dst is smaller than src")
+    _check(lib.rise_ceiling_copy(_ptr(dst), _ptr(src), n, _stream(stream)), "rise_ceiling_copy")
+
+
+def rise_ceiling_mfma_sink_floats():
+    return int(lib.rise_ceiling_mfma_sink_floats())
+
+
+def rise_ceiling_mfma(mode, iters, sink, stream=None):
+    """Back-to-back matrix instructions of `mode` ("f32", "bf16" or "fp8") on every
+    SIMD; returns the flops the launch issues (time it to get the rate)."""
+    _require_cuda(sink)
+    _require_dtype(sink, torch.float32, "sink")
+    fl = ctypes.c_double()
+    _check(lib.rise_ceiling_mfma(_mode(mode), iters, _ptr(sink), sink.numel(), ctypes.byref(fl),
+                                 _stream(stream)), "rise_ceiling_mfma")
+    return fl.value
+
+
 class Plan:
     """Owning wrapper of a rise_plan (problem arrays are kept alive with it)."""
 

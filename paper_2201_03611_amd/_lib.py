@@ -99,6 +99,9 @@ SIGNATURES = {
     "rise_autotune_gemm": (_INT, [ctypes.c_char_p, _I64, _I64, _I64, _INT, _P]),
     "rise_autotune_stencil": (_INT, [ctypes.c_char_p, _I64, _I64, _I32, _P]),
     "rise_set_tune_cache": (_INT, [ctypes.c_char_p]),
+    "rise_ceiling_copy": (_INT, [_P, _P, _SZ, _P]),
+    "rise_ceiling_mfma_sink_floats": (_SZ, []),
+    "rise_ceiling_mfma": (_INT, [_INT, _I64, _P, _SZ, ctypes.POINTER(ctypes.c_double), _P]),
     "rise_stencil2d_backward_workspace": (_SZ, [_I64, _I64, _I32, _I32]),
     "rise_stencil2d_backward": (_INT, [_P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64, _P, _I32,
                                        _I32, _INT, _P, _SZ, _P]),
