@@ -459,7 +459,7 @@ def stencil2d_iterate(img, w, steps, pad="clamp", fuse=0, out=None):
     """`steps` applications of the 2D stencil to a float32 device image; allocates
     the output and the double-buffer workspace with torch."""
     _require_dtype(img, torch.float32, "img")
-    _require_cuda(img, w)
+    _require_cuda(img)  # the small weight array may come from the host; it is copied over
     img = img.contiguous()
     w = w.contiguous().to(device=img.device, dtype=torch.float32)
     H, W = img.shape
@@ -494,7 +494,7 @@ def iterate_sum(x, n, k, *, out=None):
 @_on_stream
 def stencil2d(img, w, pad="clamp", out=None, schedule=None):
     _require_dtype(img, torch.float32, "img")
-    _require_cuda(img, w)
+    _require_cuda(img)  # the small weight array may come from the host; it is copied over
     img = img.contiguous()
     w = w.contiguous().to(device=img.device, dtype=torch.float32)
     H, W = img.shape
