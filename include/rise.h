@@ -149,6 +149,24 @@ rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const 
  * order).  Always 1 for RISE_OP_N.  Host-only; 0 for invalid sizes or opA. */
 int32_t rise_gemv_parts(int64_t M, int64_t K, rise_op opA);
 
+/* rise_gemv without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, arithmetic, results and errors as
+ * rise_gemv; the split-K partials of RISE_OP_T go to a fixed scratch array of
+ * RISE_GEMV_NOALLOC_SCRATCH_BYTES inside the library (one per device, held until
+ * the process ends; its device address is looked up on the first call on each
+ * device, with that device current).  The stream must belong to the current
+ * device.  The library allocates nothing on this path.  A split needing more
+ * than the scratch returns RISE_ERR_WORKSPACE and enqueues nothing (the
+ * library's splits never do: at most 2046 * 1024 floats).  Every call on one
+ * device shares that device's scratch, so calls that overlap in time on one
+ * device (different streams, or different threads without ordering) race and
+ * may return wrong sums; calls ordered on one stream are safe.  The scratch
+ * needs no clearing: every partial a call reads, that call wrote. */
+#define RISE_GEMV_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+rise_status rise_gemv_noalloc(float* y, const float* A, int64_t lda, rise_op opA, const float* x,
+                              int64_t M, int64_t K, void* stream);
+
 /* iterate (Sec. VI) with the tree-reduction body:
  *   out = iterate(n, m, k, split(n) |> map(reduce(+, 0)), in)
  * in: n^k * m floats (device), out: m floats (device).  Each of the k rounds

@@ -144,6 +144,17 @@ def rise_gemv(y, A, x, M, K, *, lda, opA=RISE_OP_N, ws=None, stream=None):
     _check(st, "rise_gemv")
 
 
+def rise_gemv_noalloc(y, A, x, M, K, *, lda, opA=RISE_OP_N, stream=None):
+    """rise_gemv with the split-K partials in the library's fixed per-device
+    scratch: no workspace argument, nothing allocated."""
+    _require_cuda(y, A, x)
+    st = lib.rise_gemv_noalloc(_ptr(y), _ptr(A), lda, opA, _ptr(x), M, K, _stream(stream))
+    _check(st, "rise_gemv_noalloc")
+
+
+RISE_GEMV_NOALLOC_SCRATCH_BYTES = 8 << 20
+
+
 def rise_iterate_sum_workspace(n, m, k):
     return int(lib.rise_iterate_sum_workspace(n, m, k))
 

@@ -55,6 +55,7 @@ SIGNATURES = {
     "rise_gemv_workspace": (_SZ, [_I64, _I64, _INT]),
     "rise_gemv_parts": (_I32, [_I64, _I64, _INT]),
     "rise_gemv": (_INT, [_P, _P, _I64, _INT, _P, _I64, _I64, _P, _SZ, _P]),
+    "rise_gemv_noalloc": (_INT, [_P, _P, _I64, _INT, _P, _I64, _I64, _P]),
     "rise_stencil2d_iterate_max_fuse": (_INT, []),
     "rise_stencil2d_iterate_default_fuse": (_I32, [_I32, _I32]),
     "rise_stencil2d_iterate_workspace": (_SZ, [_I64, _I64, _INT, _INT, _I64, _INT]),

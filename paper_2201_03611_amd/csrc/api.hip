@@ -345,21 +345,38 @@ size_t rise_gemv_workspace(int64_t M, int64_t K, rise_op opA) {
   return (b + 255) / 256 * 256;
 }
 
-rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const float* x,
-                      int64_t M, int64_t K, void* ws, size_t ws_bytes, void* stream) {
-  clear_error();
-  if (!dim_ok(M) || !dim_ok(K)) return fail(RISE_ERR_SHAPE, "rise_gemv: sizes must be in [0, 2^31)");
-  if (opA != RISE_OP_N && opA != RISE_OP_T) return fail(RISE_ERR_UNSUPPORTED, "rise_gemv: opA");
-  if (M == 0) return RISE_OK;
-  if (!y) return fail(RISE_ERR_NULL, "rise_gemv: y is NULL");
+// argument checks shared by rise_gemv and rise_gemv_noalloc (everything but
+// the workspace); RISE_OK with *noop set when M = 0
+static rise_status check_gemv(const char* who, float* y, const float* A, int64_t lda, rise_op opA,
+                              const float* x, int64_t M, int64_t K, bool* noop) {
+  const std::string w(who);
+  *noop = false;
+  if (!dim_ok(M) || !dim_ok(K)) return fail(RISE_ERR_SHAPE, w + ": sizes must be in [0, 2^31)");
+  if (opA != RISE_OP_N && opA != RISE_OP_T) return fail(RISE_ERR_UNSUPPORTED, w + ": opA");
+  if (M == 0) {
+    *noop = true;
+    return RISE_OK;
+  }
+  if (!y) return fail(RISE_ERR_NULL, w + ": y is NULL");
   const int64_t ar = opA == RISE_OP_N ? M : K, ac = opA == RISE_OP_N ? K : M;
   const Range ry = span(y, 1, M, M, 4);
   if (K > 0) {
-    if (!A || !x) return fail(RISE_ERR_NULL, "rise_gemv: A or x is NULL");
-    if (lda < ac) return fail(RISE_ERR_SHAPE, "rise_gemv: lda below the stored row length");
+    if (!A || !x) return fail(RISE_ERR_NULL, w + ": A or x is NULL");
+    if (lda < ac) return fail(RISE_ERR_SHAPE, w + ": lda below the stored row length");
     if (overlaps(ry, span(A, ar, ac, lda, 4)) || overlaps(ry, span(x, 1, K, K, 4)))
-      return fail(RISE_ERR_ALIAS, "rise_gemv: y overlaps A or x");
+      return fail(RISE_ERR_ALIAS, w + ": y overlaps A or x");
   }
+  return RISE_OK;
+}
+
+rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const float* x,
+                      int64_t M, int64_t K, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  bool noop = false;
+  rise_status st = check_gemv("rise_gemv", y, A, lda, opA, x, M, K, &noop);
+  if (st != RISE_OK || noop) return st;
+  const int64_t ar = opA == RISE_OP_N ? M : K, ac = opA == RISE_OP_N ? K : M;
+  const Range ry = span(y, 1, M, M, 4);
   const size_t need = gemv_workspace(M, K, opA == RISE_OP_T);
   if (need > 0) {
     if (!ws || ws_bytes < need)
@@ -373,6 +390,26 @@ rise_status rise_gemv(float* y, const float* A, int64_t lda, rise_op opA, const 
   }
   GemvArgs a{y, A, lda, opA == RISE_OP_T, x, (int)M, (int)K};
   return launch_gemv(a, ws, (hipStream_t)stream);
+}
+
+rise_status rise_gemv_noalloc(float* y, const float* A, int64_t lda, rise_op opA, const float* x,
+                              int64_t M, int64_t K, void* stream) {
+  clear_error();
+  bool noop = false;
+  rise_status st = check_gemv("rise_gemv_noalloc", y, A, lda, opA, x, M, K, &noop);
+  if (st != RISE_OK || noop) return st;
+  const size_t need = gemv_workspace(M, K, opA == RISE_OP_T);
+  if (need > gemv_scratch_bytes())
+    return fail(RISE_ERR_WORKSPACE, "rise_gemv_noalloc: split-K partials (" + std::to_string(need) +
+                                        " bytes) exceed the fixed scratch of " +
+                                        std::to_string(gemv_scratch_bytes()) + " bytes");
+  void* scratch = nullptr;
+  if (need > 0) {
+    st = gemv_scratch(&scratch);
+    if (st != RISE_OK) return st;
+  }
+  GemvArgs a{y, A, lda, opA == RISE_OP_T, x, (int)M, (int)K};
+  return launch_gemv(a, scratch, (hipStream_t)stream);
 }
 
 // n^k * m when it is below 2^40, else -1

@@ -115,6 +115,10 @@ struct GemvArgs {
 size_t gemv_workspace(int64_t M, int64_t K, bool trans);
 int gemv_parts(int64_t M, int64_t K, bool trans);
 rise_status launch_gemv(const GemvArgs& a, void* ws, hipStream_t s);
+// the fixed per-device scratch of rise_gemv_noalloc: its size, and its device
+// address on the current device (looked up on the first call per device)
+size_t gemv_scratch_bytes();
+rise_status gemv_scratch(void** out);
 rise_status launch_stencil2d_backward(const StencilBwdArgs& a, void* ws, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -19,6 +19,8 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 
 #include "common.h"
 
@@ -258,6 +260,49 @@ rise_status launch_gemv(const GemvArgs& a, void* ws, hipStream_t s) {
   hipLaunchKernelGGL(gemv_reduce, dim3((unsigned)((a.M + kThreads - 1) / kThreads)),
                      dim3(kThreads), 0, s, a.y, (const float*)ws, a.M, c.kchunks);
   return check_launch("gemv_reduce");
+}
+
+
+// ---------------------------------------------------------------------------
+// Fixed scratch for the entry point that allocates nothing (rise_gemv_noalloc).
+// The split-K partials of the transposed product go to this file-scope device
+// array instead of a caller workspace.  Its size covers every split col_split
+// picks: kchunks > 1 only when there are at most 1023 column blocks, and then
+// kchunks * M <= ceil(1024 / mblocks) * mblocks * 1024 <= 2046 * 1024 floats.
+// Each device holds its own copy for the life of the process; its device
+// address is looked up once per device (hipGetSymbolAddress with that device
+// current) and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kGemvScratchBytes = RISE_GEMV_NOALLOC_SCRATCH_BYTES;
+static_assert(kGemvScratchBytes >= (size_t)2046 * kColsPerBlock * 4, "scratch below the largest split");
+static __device__ __align__(256) unsigned char scratch[kGemvScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+}  // namespace
+
+size_t gemv_scratch_bytes() { return kGemvScratchBytes; }
+
+rise_status gemv_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RISE_ERR_HIP, "rise_gemv_noalloc: hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) return fail(RISE_ERR_HIP, "rise_gemv_noalloc: device index above 63");
+  void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(RISE_ERR_HIP, std::string("rise_gemv_noalloc: hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+      g_scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return RISE_OK;
 }
 
 }  // namespace rise

@@ -96,6 +96,36 @@ def test_gemv_rejections(lib):
     assert gemv(lib, M=0, y=None) == 0                  # no-op
 
 
+def test_gemv_noalloc_rejections(lib):
+    # the same host-side checks as rise_gemv, minus the workspace (none is passed)
+    def call(y=FAKE_C, A=FAKE_A, lda=64, opA=0, x=FAKE_B, M=64, K=64):
+        return lib.rise_gemv_noalloc(y, A, lda, opA, x, M, K, None)
+
+    assert call(y=None) == 1                            # NULL
+    assert call(x=None) == 1
+    assert call(M=-1) == 2                              # SHAPE
+    assert call(K=1 << 31) == 2
+    assert call(lda=63) == 2
+    assert call(opA=1, M=100, lda=99) == 2
+    assert call(y=FAKE_A + 128) == 3                    # ALIAS: y inside A
+    assert call(opA=3) == 5                             # UNSUPPORTED
+    assert call(M=0, y=None) == 0                       # no-op
+    msg = lib.rise_last_error()
+    assert msg in (None, b"")
+
+
+def test_gemv_noalloc_scratch_covers_every_split(lib):
+    # the library's largest split-K partial buffer fits the fixed scratch:
+    # kchunks > 1 needs at most 1023 column blocks of 1024 outputs
+    from paper_2201_03611_amd import RISE_GEMV_NOALLOC_SCRATCH_BYTES as cap
+
+    worst = 0
+    for M in [1, 1000, 1024, 1025, 4096, 16384, 100000, 1023 * 1024, 1023 * 1024 + 1, 1 << 20]:
+        for K in [1, 64, 65, 4096, 1 << 20, (1 << 31) - 1]:
+            worst = max(worst, lib.rise_gemv_workspace(M, K, 1))
+    assert 0 < worst <= cap
+
+
 def iterate(lib, out=FAKE_C, x=FAKE_A, n=2, m=1, k=26, ws=None, ws_bytes=0):
     return lib.rise_iterate_sum(out, x, n, m, k, ws, ws_bytes, None)
 
