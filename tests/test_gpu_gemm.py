@@ -107,6 +107,50 @@ def test_padded_rows_ragged_edges_every_tile(rise, ops, M, N, K):
         assert componentwise(host(C), ref, gemm_scale(A, B)) <= TOL_F32, tile
 
 
+@pytest.mark.parametrize("ops", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("M,N,K", [(260, 132, 48), (300, 200, 16), (516, 388, 272),
+                                   (4, 4, 16)])
+def test_async_ring_ragged_mn_integer_exact(rise, ops, M, N, K):
+    # K a multiple of 16 with 16-byte rows: the 256 x 128 x 16 tile runs the
+    # asynchronous-ring schedule (rows and chunks past M and N are fetched from
+    # the last valid ones and only feed outputs that are not stored); integer
+    # inputs make every summation order exact, so the result is bit for bit
+    g = ri.rng(M + 3 * N + 7 * K + 11 * ops[0] + 13 * ops[1])
+    A = ri.integer_matrix(g, M, K, bound=3)
+    B = ri.integer_matrix(g, K, N, bound=3)
+    As = np.ascontiguousarray(A.T) if ops[0] else A
+    Bs = np.ascontiguousarray(B.T) if ops[1] else B
+    C = run(rise, As, Bs, transA=ops[0], transB=ops[1], tile=(256, 128, 16))
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+    assert np.array_equal(C, exact)
+
+
+@pytest.mark.parametrize("ops", [(False, False), (False, True), (True, False), (True, True)])
+def test_async_ring_nan_padded_rows_oracle(rise, ops):
+    # leading dimensions beyond the rows with NaN in the padding: a copy that
+    # reached past a row (or a chunk past M or N not clamped) would poison C
+    import torch
+
+    M, N, K = 388, 260, 96
+    g = ri.rng(17 + 2 * ops[0] + ops[1])
+    A = ri.uniform_matrix(g, M, K)
+    B = ri.uniform_matrix(g, K, N)
+
+    def padded(X):
+        r, c = X.shape
+        P = np.full((r, c + 8), np.nan, np.float32)
+        P[:, :c] = X
+        return P
+
+    As = padded(np.ascontiguousarray(A.T) if ops[0] else A)
+    Bs = padded(np.ascontiguousarray(B.T) if ops[1] else B)
+    C = torch.full((M, N), float("nan"), device="cuda", dtype=torch.float32)
+    print(f"gemm async ring padded ops={ops}", flush=True)
+    rise.rise_gemm(C, dev(As), dev(Bs), M, N, K, lda=As.shape[1], ldb=Bs.shape[1], ldc=N,
+                   opA=int(ops[0]), opB=int(ops[1]), tile=(256, 128, 16))
+    assert componentwise(host(C), oracle.gemm(A, B), gemm_scale(A, B)) <= TOL_F32
+
+
 def test_k_zero_writes_zero(rise):
     import torch
 
