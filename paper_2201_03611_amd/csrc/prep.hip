@@ -10,9 +10,10 @@
 //            amax * 2^e <= 448 (0 for an all-zero block), q = e4m3(a * 2^e)
 //            (round to nearest even), scale byte 127 - e (E8M0 of 2^-e).
 //
-// Each workgroup transposes a 64 x 64 (rows x K) tile through LDS so that both
-// the read (along whichever source dimension is contiguous) and the write
-// (along K) are coalesced.
+// A source whose rows are K-contiguous streams straight through (bf16 modes);
+// otherwise each workgroup transposes a 64 x 64 (rows x K) tile through LDS so
+// that both the read (along whichever source dimension is contiguous) and the
+// write (along K) are coalesced.
 #include "gemm_lowp.h"
 
 namespace rise {
@@ -211,6 +212,53 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(void* __restrict__ out, 
   }
 }
 
+// Source rows already K-contiguous (ld_k == 1, 16-byte aligned rows): no
+// transpose is needed, so the bf16 modes stream without LDS.  Each thread
+// converts 8 consecutive K of one row (two 16-byte loads, one 16-byte store
+// per part); consecutive lanes take consecutive chunks of a row, so a wave
+// reads 2 KB and writes 1 KB per part contiguously.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void prep_stream_kernel(
+    void* __restrict__ out, int64_t rows_out, int64_t k_out, const float* __restrict__ src,
+    int64_t rows, int64_t K, int64_t ld_r, int vec_out) {
+  const int64_t chunks = (k_out + 7) / 8;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= rows_out * chunks) return;
+  const int64_t gr = t / chunks, gk = (t - gr * chunks) * 8;
+  float x[8];
+  if (gr < rows && gk + 8 <= K) {
+    const f32x4* q = reinterpret_cast<const f32x4*>(src + gr * ld_r + gk);
+    const f32x4 v0 = q[0], v1 = q[1];
+    x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
+    x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; e++) x[e] = (gr < rows && gk + e < K) ? src[gr * ld_r + gk + e] : 0.f;
+  }
+  constexpr int PARTS = MODE == RISE_MODE_BF16 ? 1 : MODE == RISE_MODE_BF16X3 ? 2 : 3;
+  const int64_t plane = rows_out * k_out;
+#pragma unroll
+  for (int p = 0; p < PARTS; p++) {
+    uint16_t h[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      h[e] = bf16_rne(x[e]);
+      x[e] = x[e] - bf16_to_f32(h[e]);  // exact residual
+    }
+    uint16_t* o = reinterpret_cast<uint16_t*>(out) + p * plane + gr * k_out + gk;
+    if (vec_out && gk + 8 <= k_out) {
+      i32x4 v;
+#pragma unroll
+      for (int w = 0; w < 4; w++) v[w] = (int)((uint32_t)h[2 * w] | ((uint32_t)h[2 * w + 1] << 16));
+      *reinterpret_cast<i32x4*>(o) = v;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; e++)
+        if (gk + e < k_out) o[e] = h[e];
+    }
+  }
+}
+
 template <typename SRC, int MODE>
 rise_status launch_mode(const PrepArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.rows_out + TR - 1) / TR), (unsigned)((a.k_out + TK - 1) / TK));
@@ -223,6 +271,13 @@ rise_status launch_mode(const PrepArgs& a, hipStream_t s) {
   if (sizeof(SRC) == 4 && aligned(a.src)) {
     if (a.ld_k == 1 && a.ld_r % 4 == 0) layout = 1;
     else if (a.ld_r == 1 && a.ld_k % 4 == 0) layout = 2;
+  }
+  if (layout == 1 && MODE != RISE_MODE_FP8) {
+    const int64_t threads = a.rows_out * ((a.k_out + 7) / 8);
+    hipLaunchKernelGGL((prep_stream_kernel<MODE>), dim3((unsigned)((threads + kThreads - 1) / kThreads)),
+                       block, 0, s, a.out, a.rows_out, a.k_out, reinterpret_cast<const float*>(a.src),
+                       a.rows, a.K, a.ld_r, vec_out);
+    return check_launch("prep_stream_kernel");
   }
   if (layout == 1)
     hipLaunchKernelGGL((prep_kernel<SRC, MODE, 1>), grid, block, 0, s, a.out, a.rows_out, a.k_out,
