@@ -3,12 +3,16 @@
 // The batch is the outer map of the patterns: every (problem, output tile) pair
 // is an independent work item (distinct output acceptors, paper Sec. V-C), so
 // the items can run in any order.  The host builds a table of problem
-// descriptors and a flat list of work items sorted by estimated cost (largest
-// first), picks a tile shape for every GEMM from a measured cost table, and
-// captures  [reset counter] -> [persistent kernel]  in a HIP graph.  Every
-// persistent workgroup repeatedly takes the next item with one atomic add and
-// runs the matching tile function (tiles.h) on a shared LDS buffer, so a batch
-// costs one launch instead of one per problem.
+// descriptors and the work items, picks a tile shape for every GEMM from a
+// measured cost table, and captures one graph of persistent kernels, one per
+// class of tile, each with the registers and occupancy its tile needs:
+//   [reset counter] -> [GEMM tiles] -> [stencil tiles, one kernel per window
+//   side and load width present]
+// In the GEMM kernel every workgroup repeatedly takes the next item (largest
+// estimated cost first) with one atomic add and runs the matching tile function
+// (tiles.h); the stencil tiles of one class cost the same, so the stencil
+// kernels walk their item list round-robin without a counter.  A batch costs
+// one graph launch instead of one launch per problem.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -37,23 +41,20 @@ enum Kind : int {
 struct KindShape {
   int bm, bn, bk;
 };
-// Three resident workgroups per CU: the many small tiles of a batch are
-// latency-bound, and more workgroups in flight hide that latency.  For the
-// LDS to allow it (a third of 160 KB per workgroup) the FP32 slabs here are 16
-// deep, not the 32 of the one-problem kernels.  The GEMM tile kinds are
-// separate, non-inlined functions with their own register allocation, so the
-// kernel's 168 registers need to hold only the stencil tiles (measured on the
-// 512 GEMM + 256 stencil batch: 3.8 ms against 4.6 ms with two workgroups per
-// CU and every kind inlined).
+// The GEMM kernel keeps the FP32 slabs 16 deep (LDS for several resident
+// workgroups); its tile kinds are separate, non-inlined functions with their
+// own register allocation.  Stencil tiles are 8 output rows x 256 columns for
+// windows up to 5 x 5 and 16 rows for 7 x 7, the one-problem kernel's choice.
 constexpr int kF32BK = 16;
-constexpr int kOccupancy = 3;
+constexpr int kGemmOccupancy = 2;
+constexpr int stencil_rows(int k) { return k <= 5 ? 8 : 16; }
 const KindShape kShape[NUM_KINDS] = {
     {64, 64, kF32BK}, {64, 64, kF32BK}, {128, 64, kF32BK}, {128, 64, kF32BK},
     {64, 128, kF32BK}, {64, 128, kF32BK}, {128, 128, kF32BK}, {128, 128, kF32BK},
     {64, 64, 32}, {64, 64, 32}, {128, 128, 32}, {128, 128, 32},
-    {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0},
-    {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}};
-constexpr int kStencilRows = 16;
+    {8, 256, 0}, {8, 256, 0}, {8, 256, 0}, {16, 256, 0},
+    {8, 256, 0}, {8, 256, 0}, {8, 256, 0}, {16, 256, 0}};
+constexpr int kStencilClasses = NUM_KINDS - STENCIL_1;  // side x load width
 
 struct Desc {  // one problem
   float* out;
@@ -71,13 +72,12 @@ struct Item {
 };
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-// the largest tile of any kind
-constexpr int kLdsBytes =
+// the largest GEMM tile of any kind
+constexpr int kGemmLdsBytes =
     cmax(cmax(4 * tiles::F32Cfg<128, 128, kF32BK, false, false>::LDS_FLOATS,
               4 * tiles::F32Cfg<128, 128, kF32BK, false, true>::LDS_FLOATS),
-         cmax(16 * tiles::Bf16Cfg<128, 128, 32>::LDS_CHUNKS,
-              16 * tiles::StencilCfg<7, kStencilRows>::LDS_CHUNKS));
-static_assert(kLdsBytes * kOccupancy <= 160 * 1024, "LDS of the resident workgroups");
+         16 * tiles::Bf16Cfg<128, 128, 32>::LDS_CHUNKS);
+static_assert(kGemmLdsBytes * kGemmOccupancy <= 160 * 1024, "LDS of the resident workgroups");
 
 template <int BM, int BN, bool TB>
 __device__ __noinline__ void item_f32(const Desc& d, int tm, int tn, char* lds) {
@@ -92,15 +92,7 @@ __device__ __noinline__ void item_bf16(const Desc& d, int tm, int tn, char* lds)
                                         d.lda, reinterpret_cast<const uint16_t*>(d.b), d.ldb, d.M,
                                         d.N, d.K, tm * BM, tn * BN, reinterpret_cast<i32x4*>(lds));
 }
-template <int K, bool VEC>
-__device__ __forceinline__ void item_stencil(const Desc& d, int tm, int tn, char* lds) {
-  tiles::stencil_lds_tile<K, VEC, kStencilRows>(
-      d.out, d.ldc, reinterpret_cast<const float*>(d.a), d.lda, d.M, d.N,
-      reinterpret_cast<const float*>(d.b), d.zero_pad, tm * kStencilRows, tn * tiles::kStencilTX,
-      reinterpret_cast<f32x4*>(lds));
-}
-
-__device__ __forceinline__ void run_item(const Desc& d, int tile, char* lds) {
+__device__ __forceinline__ void run_gemm_item(const Desc& d, int tile, char* lds) {
   const int tm = tile / d.tiles_n, tn = tile - tm * d.tiles_n;
   switch (d.kind) {
     case F32_64x64_N: item_f32<64, 64, false>(d, tm, tn, lds); break;
@@ -115,14 +107,6 @@ __device__ __forceinline__ void run_item(const Desc& d, int tile, char* lds) {
     case BF16_64x64_T: item_bf16<64, 64, true>(d, tm, tn, lds); break;
     case BF16_128x128_N: item_bf16<128, 128, false>(d, tm, tn, lds); break;
     case BF16_128x128_T: item_bf16<128, 128, true>(d, tm, tn, lds); break;
-    case STENCIL_1: item_stencil<1, true>(d, tm, tn, lds); break;
-    case STENCIL_3: item_stencil<3, true>(d, tm, tn, lds); break;
-    case STENCIL_5: item_stencil<5, true>(d, tm, tn, lds); break;
-    case STENCIL_7: item_stencil<7, true>(d, tm, tn, lds); break;
-    case STENCIL_1S: item_stencil<1, false>(d, tm, tn, lds); break;
-    case STENCIL_3S: item_stencil<3, false>(d, tm, tn, lds); break;
-    case STENCIL_5S: item_stencil<5, false>(d, tm, tn, lds); break;
-    case STENCIL_7S: item_stencil<7, false>(d, tm, tn, lds); break;
     default: break;
   }
 }
@@ -135,10 +119,9 @@ __global__ void reset_counter(int* counter) {
 // (item >= n_items) is reached by every workgroup because the counter only grows.
 // The index of the following item is requested (thread 0, one atomic) while the
 // current item runs, so the atomic's round trip is off the critical path.
-__global__ __launch_bounds__(kThreads, kOccupancy) void batched_kernel(const Desc* __restrict__ descs,
-                                                              const Item* __restrict__ items,
-                                                              int n_items, int* counter) {
-  __shared__ __attribute__((aligned(16))) char lds[kLdsBytes];
+__global__ __launch_bounds__(kThreads, kGemmOccupancy) void batched_gemm_kernel(
+    const Desc* __restrict__ descs, const Item* __restrict__ items, int n_items, int* counter) {
+  __shared__ __attribute__((aligned(16))) char lds[kGemmLdsBytes];
   __shared__ int next;
   if (threadIdx.x == 0) next = atomicAdd(counter, 1);
   __syncthreads();
@@ -149,10 +132,54 @@ __global__ __launch_bounds__(kThreads, kOccupancy) void batched_kernel(const Des
     int pre = 0;
     if (threadIdx.x == 0) pre = atomicAdd(counter, 1);  // the following item
     const Item item = items[it];
-    run_item(descs[item.desc], item.tile, lds);
+    run_gemm_item(descs[item.desc], item.tile, lds);
     if (threadIdx.x == 0) next = pre;
     __syncthreads();  // the LDS buffer is free for the next item; `next` is visible
     it = next;
+  }
+}
+
+// Stencil tiles of one window side and load width: workgroup b runs items b,
+// b + grid, b + 2 grid, ... (the items of a class cost the same).
+// resident workgroups per CU: as many as the tile's registers allow without
+// spilling (the item loop needs a few registers more than the one-problem
+// kernels' 64 for 5 x 5 and 126 for 7 x 7)
+constexpr int stencil_occupancy(int k) { return k <= 3 ? 8 : k == 5 ? 5 : 3; }
+
+template <int K, bool VEC>
+__global__ __launch_bounds__(kThreads, stencil_occupancy(K)) void batched_stencil_kernel(const Desc* __restrict__ descs,
+                                                                   const Item* __restrict__ items,
+                                                                   int n_items) {
+  constexpr int TY = stencil_rows(K);
+  __shared__ f32x4 lds[tiles::StencilCfg<K, TY>::LDS_CHUNKS];
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    // the item and its descriptor are the same for every lane: scalar registers
+    const int desc = __builtin_amdgcn_readfirstlane(items[i].desc);
+    const int tile = __builtin_amdgcn_readfirstlane(items[i].tile);
+    const Desc& d = descs[desc];
+    const int tm = tile / d.tiles_n, tn = tile - tm * d.tiles_n;
+    tiles::stencil_lds_tile<K, VEC, TY, true, true>(
+        d.out, d.ldc, reinterpret_cast<const float*>(d.a), d.lda, d.M, d.N,
+        reinterpret_cast<const float*>(d.b), d.zero_pad, tm * TY, tn * tiles::kStencilTX, lds);
+    __syncthreads();  // every wave is done with the LDS tile before the next item fills it
+  }
+}
+
+template <int K, bool VEC>
+const void* stencil_kernel_ptr() {
+  return reinterpret_cast<const void*>(&batched_stencil_kernel<K, VEC>);
+}
+// class c = kind - STENCIL_1: sides 1, 3, 5, 7 with 16-byte loads, then scalar
+const void* stencil_class_kernel(int c) {
+  switch (c) {
+    case 0: return stencil_kernel_ptr<1, true>();
+    case 1: return stencil_kernel_ptr<3, true>();
+    case 2: return stencil_kernel_ptr<5, true>();
+    case 3: return stencil_kernel_ptr<7, true>();
+    case 4: return stencil_kernel_ptr<1, false>();
+    case 5: return stencil_kernel_ptr<3, false>();
+    case 6: return stencil_kernel_ptr<5, false>();
+    default: return stencil_kernel_ptr<7, false>();
   }
 }
 
@@ -269,16 +296,59 @@ rise_status check_stencil_problem(const rise_stencil_problem& p, int i) {
 
 }  // namespace
 
+// one kernel of a plan: items [first, first + count) of the item list;
+// cls = -1 is the GEMM kernel, else the stencil class (kind - STENCIL_1)
+struct Launch {
+  int cls, first, count, grid;
+};
+
+// Concurrent classes: the stencil kernels run on a second stream of the plan
+// (forked from and joined back to the launch stream, default priority) while
+// the GEMM kernel, one workgroup per CU, leaves room on every CU for stencil
+// workgroups; the matrix-core-bound and HBM-bound tiles then overlap.
+constexpr bool kConcurrentClasses = false;
+
 struct PlanImpl {
   Desc* d_desc = nullptr;
   Item* d_items = nullptr;
   int* d_counter = nullptr;
-  int n_items = 0, grid = 0;
+  int n_items = 0;
+  std::vector<Launch> launches;
+  hipStream_t aux = nullptr;  // the stencil kernels' stream (kConcurrentClasses)
+  hipEvent_t fork = nullptr, join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<int> kinds;  // chosen kind per problem (GEMMs first, then stencils)
   double est_us = 0;
 };
+
+namespace {
+// [reset counter] -> the plan's kernels, in order on one stream; the first
+// launch error, if any
+hipError_t enqueue(const PlanImpl* p, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, p->d_counter);
+  hipError_t e = hipGetLastError();
+  const bool fork = p->aux != nullptr;
+  if (fork && e == hipSuccess) e = hipEventRecord(p->fork, s);
+  if (fork && e == hipSuccess) e = hipStreamWaitEvent(p->aux, p->fork, 0);
+  for (const Launch& l : p->launches) {
+    if (e != hipSuccess) break;
+    const Item* items = p->d_items + l.first;
+    if (l.cls < 0) {
+      hipLaunchKernelGGL(batched_gemm_kernel, dim3(l.grid), dim3(kThreads), 0, s, p->d_desc, items,
+                         l.count, p->d_counter);
+      e = hipGetLastError();
+    } else {
+      void* args[] = {(void*)&p->d_desc, (void*)&items, (void*)&l.count};
+      e = hipLaunchKernel(stencil_class_kernel(l.cls), dim3(l.grid), dim3(kThreads), args, 0,
+                          fork ? p->aux : s);
+    }
+  }
+  if (fork && e == hipSuccess) e = hipEventRecord(p->join, p->aux);
+  if (fork && e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
+  return e;
+}
+}  // namespace
 
 rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
                        const rise_stencil_problem* st, int ns, const char* tune_path,
@@ -322,48 +392,54 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
     Desc d{p.out, p.in, p.w, p.ld_in, 0, p.ld_out, (int)p.H, (int)p.W, p.k, kind,
            ceil_div(p.W, tiles::kStencilTX), p.pad == RISE_PAD_ZERO, 0};
     descs.push_back(d);
-    ntile.push_back((p.H == 0 || p.W == 0) ? 0 : ceil_div(p.H, kStencilRows) * d.tiles_n);
+    ntile.push_back((p.H == 0 || p.W == 0) ? 0 : ceil_div(p.H, kShape[kind].bm) * d.tiles_n);
     unit.push_back(cost[kind].a);
   }
-  // Each class (matrix-core-bound GEMM tiles, HBM-bound stencil tiles) in
-  // longest-processing-time order, so the tail of the launch is made of the
-  // cheapest items; the two lists are then merged in proportion to their
-  // estimated time, so that at any moment both kinds of tile are in flight and
-  // the stencils' memory traffic overlaps the GEMMs' arithmetic.
+  // GEMM tiles in longest-processing-time order (largest estimated cost first,
+  // so the tail of the GEMM kernel is made of the cheapest tiles), then the
+  // stencil tiles grouped by class (window side, load width), each group one
+  // kernel.
   std::vector<int> order(descs.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return unit[x] > unit[y]; });
-  std::vector<Item> cls[2];
-  std::vector<double> cls_us[2];
-  double total[2] = {0.0, 0.0};
-  for (int d : order) {
-    const int c = descs[d].kind >= STENCIL_1 ? 1 : 0;
-    plan->est_us += unit[d] * ntile[d];
-    total[c] += unit[d] * ntile[d];
-    for (int t = 0; t < ntile[d]; t++) {
-      cls[c].push_back(Item{d, t});
-      cls_us[c].push_back(unit[d]);
-    }
-  }
   std::vector<Item> items;
-  items.reserve(cls[0].size() + cls[1].size());
-  size_t next[2] = {0, 0};
-  double done[2] = {0.0, 0.0};
-  while (next[0] < cls[0].size() || next[1] < cls[1].size()) {
-    int c;
-    if (next[0] >= cls[0].size()) c = 1;
-    else if (next[1] >= cls[1].size()) c = 0;
-    else c = done[0] / total[0] <= done[1] / total[1] ? 0 : 1;
-    items.push_back(cls[c][next[c]]);
-    done[c] += cls_us[c][next[c]];
-    next[c]++;
+  for (int d : order) {
+    plan->est_us += unit[d] * ntile[d];
+    if (descs[d].kind < STENCIL_1)
+      for (int t = 0; t < ntile[d]; t++) items.push_back(Item{d, t});
+  }
+  const int n_gemm_items = (int)items.size();
+  int stencil_first[kStencilClasses], stencil_count[kStencilClasses];
+  for (int c = 0; c < kStencilClasses; c++) {
+    stencil_first[c] = (int)items.size();
+    for (int d : order)
+      if (descs[d].kind == STENCIL_1 + c)
+        for (int t = 0; t < ntile[d]; t++) items.push_back(Item{d, t});
+    stencil_count[c] = (int)items.size() - stencil_first[c];
   }
   plan->n_items = (int)items.size();
 
   int dev = 0, cus = 256;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  plan->grid = std::max(1, std::min(plan->n_items, kOccupancy * cus));
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  bool any_stencil = false;
+  for (int c = 0; c < kStencilClasses; c++) any_stencil |= stencil_count[c] > 0;
+  const bool concurrent = kConcurrentClasses && n_gemm_items > 0 && any_stencil;
+  const int gemm_per_cu = concurrent ? 1 : kGemmOccupancy;
+  if (n_gemm_items > 0)
+    plan->launches.push_back(
+        Launch{-1, 0, n_gemm_items, std::max(1, std::min(n_gemm_items, gemm_per_cu * cus))});
+  for (int c = 0; c < kStencilClasses; c++) {
+    if (stencil_count[c] == 0) continue;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stencil_class_kernel(c), kThreads, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    plan->launches.push_back(Launch{c, stencil_first[c], stencil_count[c],
+                                    std::max(1, std::min(stencil_count[c], per_cu * cus))});
+  }
 
   hipError_t e = hipSuccess;
   const size_t nd = std::max<size_t>(descs.size(), 1), ni = std::max<size_t>(items.size(), 1);
@@ -380,7 +456,15 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
     rise_plan_free(plan);
     return fail(RISE_ERR_HIP, std::string("rise_plan_create: ") + hipGetErrorString(e));
   }
-  // capture [reset counter] -> [persistent kernel] on a private stream
+  if (concurrent) {
+    if ((e = hipStreamCreateWithFlags(&plan->aux, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&plan->fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&plan->join, hipEventDisableTiming)) != hipSuccess) {
+      rise_plan_free(plan);
+      return fail(RISE_ERR_HIP, std::string("rise_plan_create: ") + hipGetErrorString(e));
+    }
+  }
+  // capture the plan's kernels on a private stream
   hipStream_t cap;
   if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) {
     rise_plan_free(plan);
@@ -388,14 +472,12 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
   }
   e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, cap, plan->d_counter);
-    if (plan->n_items > 0)
-      hipLaunchKernelGGL(batched_kernel, dim3(plan->grid), dim3(kThreads), 0, cap, plan->d_desc,
-                         plan->d_items, plan->n_items, plan->d_counter);
+    const hipError_t le = enqueue(plan, cap);
     e = hipStreamEndCapture(cap, &plan->graph);
+    if (e == hipSuccess) e = le;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
-  hipStreamDestroy(cap);
+  (void)hipStreamDestroy(cap);
   if (e != hipSuccess) {
     rise_plan_free(plan);
     return fail(RISE_ERR_HIP, std::string("rise_plan_create: graph: ") + hipGetErrorString(e));
@@ -412,25 +494,28 @@ rise_status plan_launch(PlanImpl* p, hipStream_t s) {
 }
 
 rise_status plan_launch_direct(PlanImpl* p, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, p->d_counter);
-  if (p->n_items > 0)
-    hipLaunchKernelGGL(batched_kernel, dim3(p->grid), dim3(kThreads), 0, s, p->d_desc, p->d_items,
-                       p->n_items, p->d_counter);
-  return check_launch("batched_kernel");
+  const hipError_t e = enqueue(p, s);
+  if (e != hipSuccess)
+    return fail(RISE_ERR_HIP, std::string("rise_plan_launch_direct: ") + hipGetErrorString(e));
+  return RISE_OK;
 }
 
 void rise_plan_free(PlanImpl* p) {
   if (!p) return;
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
-  if (p->d_desc) hipFree(p->d_desc);
-  if (p->d_items) hipFree(p->d_items);
-  if (p->d_counter) hipFree(p->d_counter);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->d_desc) (void)hipFree(p->d_desc);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_counter) (void)hipFree(p->d_counter);
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->join) (void)hipEventDestroy(p->join);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
 }
 
 int plan_items(const PlanImpl* p) { return p->n_items; }
-int plan_grid(const PlanImpl* p) { return p->grid; }
+// workgroups of the plan's first kernel (a plan of one tile class has one)
+int plan_grid(const PlanImpl* p) { return p->launches.empty() ? 1 : p->launches[0].grid; }
 double plan_estimate(const PlanImpl* p) { return p->est_us; }
 int plan_kind(const PlanImpl* p, int i) { return i >= 0 && i < (int)p->kinds.size() ? p->kinds[i] : -1; }
 const char* kind_name(int k) { return k >= 0 && k < NUM_KINDS ? kKindNames[k] : ""; }

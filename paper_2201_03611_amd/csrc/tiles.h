@@ -357,8 +357,14 @@ struct StencilCfg {
 template <int K, int TY>
 using StencilRegs = f32x4[StencilCfg<K, TY>::PER];  // one thread's share of a halo tile
 
+// a 16-byte vector of floats that may sit at any 4-byte boundary (gfx950 runs
+// global memory in unaligned-access mode: one dwordx4 access either way)
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
 // Global -> registers: the (TY + 2R) x (256 + 8) halo tile of output rows
 // [y0, y0 + TY), columns [x0, x0 + 256), with pad2D applied as index remapping.
+// Chunks wholly inside the image row are one 16-byte load (aligned when VEC,
+// otherwise at the row's own 4-byte alignment); edge chunks go element-wise.
 template <int K, bool VEC, int TY>
 __device__ __forceinline__ void stencil_fetch(StencilRegs<K, TY>& st,
                                               const float* __restrict__ in, int64_t ld_in,
@@ -380,8 +386,11 @@ __device__ __forceinline__ void stencil_fetch(StencilRegs<K, TY>& st,
       }
       if (row_ok) {
         const float* rp = in + (int64_t)gy * ld_in;
-        if (VEC && gx >= 0 && gx + 3 < W) {
-          v = *reinterpret_cast<const f32x4*>(rp + gx);
+        if (gx >= 0 && gx + 3 < W) {
+          if (VEC)
+            v = *reinterpret_cast<const f32x4*>(rp + gx);
+          else
+            v = *reinterpret_cast<const f32x4u*>(rp + gx);
         } else {
           float e[4];
 #pragma unroll
@@ -505,7 +514,8 @@ __device__ __forceinline__ void stencil_compute(float (&res)[TY / 4][4], const f
     }
 }
 
-// join: 16-byte row stores of the wave's outputs (guarded at the image edge).
+// join: 16-byte row stores of the wave's outputs (guarded at the image edge;
+// rows that are not 16-byte aligned use unaligned 16-byte stores).
 // NT selects non-temporal stores (the output is not read again by this pass).
 template <bool VEC, int TY, bool NT>
 __device__ __forceinline__ void stencil_store(float* __restrict__ out, int64_t ld_out, int H,
@@ -519,12 +529,20 @@ __device__ __forceinline__ void stencil_store(float* __restrict__ out, int64_t l
     const int y = y0 + wave * RW + o;
     if (y < H) {
       float* op = out + (int64_t)y * ld_out;
-      if (VEC && x + 3 < W) {
-        const f32x4 v = f32x4{res[o][0], res[o][1], res[o][2], res[o][3]};
-        if (NT)
-          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(op + x));
-        else
-          *reinterpret_cast<f32x4*>(op + x) = v;
+      if (x + 3 < W) {
+        if (VEC) {
+          const f32x4 v = f32x4{res[o][0], res[o][1], res[o][2], res[o][3]};
+          if (NT)
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(op + x));
+          else
+            *reinterpret_cast<f32x4*>(op + x) = v;
+        } else {
+          const f32x4u v = f32x4u{res[o][0], res[o][1], res[o][2], res[o][3]};
+          if (NT)
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4u*>(op + x));
+          else
+            *reinterpret_cast<f32x4u*>(op + x) = v;
+        }
       } else {
 #pragma unroll
         for (int q = 0; q < 4; q++)
@@ -543,18 +561,26 @@ __device__ __forceinline__ void stencil_compute_store(float* __restrict__ out, i
   stencil_store<VEC, TY, NT>(out, ld_out, H, W, res, y0, x0);
 }
 
-template <int K>
+// SCALAR: the weight pointer is read from memory (not a kernel argument), so
+// the compiler cannot tell it is the same for every lane; the values are moved
+// to scalar registers explicitly instead of occupying k*k vector registers.
+template <int K, bool SCALAR = false>
 __device__ __forceinline__ void stencil_weights(float (&wt)[K][K], const float* __restrict__ w) {
 #pragma unroll
   for (int dy = 0; dy < K; dy++)
 #pragma unroll
-    for (int dx = 0; dx < K; dx++) wt[dy][dx] = w[dy * K + dx];
+    for (int dx = 0; dx < K; dx++) {
+      const float v = w[dy * K + dx];
+      wt[dy][dx] = SCALAR ? __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                          __builtin_bit_cast(int, v)))
+                          : v;
+    }
 }
 
 // One tile, start to finish (fetch, stage, barrier, compute, store).
 // NT: non-temporal output stores (the output is not read again soon); without
 // it the output stays in the caches for a consumer that reads it next.
-template <int K, bool VEC, int TY, bool NT = true>
+template <int K, bool VEC, int TY, bool NT = true, bool SCALAR_W = false>
 __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_t ld_out,
                                                  const float* __restrict__ in, int64_t ld_in,
                                                  int H, int W, const float* __restrict__ w,
@@ -582,7 +608,7 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
   }
   __syncthreads();
   float wt[K][K];
-  stencil_weights<K>(wt, w);
+  stencil_weights<K, SCALAR_W>(wt, w);
   stencil_compute_store<K, VEC, TY, NT>(out, ld_out, H, W, wt, y0, x0, lds);
 }
 
