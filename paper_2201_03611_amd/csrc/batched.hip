@@ -56,10 +56,10 @@ const KindShape kShape[NUM_KINDS] = {
     {8, 256, 0}, {8, 256, 0}, {8, 256, 0}, {16, 256, 0}};
 constexpr int kStencilClasses = NUM_KINDS - STENCIL_1;  // side x load width
 
-struct Desc {  // one problem
-  float* out;
-  const void* a;   // GEMM A / stencil input
-  const void* b;   // GEMM B / stencil weights
+struct Desc {  // one problem; device addresses as integers (see gptr)
+  uint64_t out;
+  uint64_t a;      // GEMM A / stencil input
+  uint64_t b;      // GEMM B / stencil weights
   int64_t lda, ldb, ldc;  // stencil: lda = ld_in, ldc = ld_out
   int M, N, K;            // stencil: M = H, N = W, K = window side
   int kind;
@@ -72,25 +72,44 @@ struct Item {
 };
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// FP32 tiles of problems whose storage allows it (tiles::f32_async_eligible)
+// run the asynchronous-ring schedule with this many slabs in flight
+constexpr int kF32Stages = 3;
 // the largest GEMM tile of any kind
 constexpr int kGemmLdsBytes =
-    cmax(cmax(4 * tiles::F32Cfg<128, 128, kF32BK, false, false>::LDS_FLOATS,
-              4 * tiles::F32Cfg<128, 128, kF32BK, false, true>::LDS_FLOATS),
+    cmax(cmax(cmax(4 * tiles::F32Cfg<128, 128, kF32BK, false, false>::LDS_FLOATS,
+                   4 * tiles::F32Cfg<128, 128, kF32BK, false, true>::LDS_FLOATS),
+              16 * tiles::F32AsyncCfg<128, 128, kF32Stages>::LDS_CHUNKS),
          16 * tiles::Bf16Cfg<128, 128, 32>::LDS_CHUNKS);
 static_assert(kGemmLdsBytes * kGemmOccupancy <= 160 * 1024, "LDS of the resident workgroups");
 
+// A descriptor address as a pointer into global memory: built from the integer
+// through the global address space, so the compiler uses global (not flat)
+// memory instructions even in the separately compiled item functions.
+template <typename T>
+__device__ __forceinline__ T* gptr(uint64_t v) {
+  return (T*)((__attribute__((address_space(1))) T*)v);
+}
+
 template <int BM, int BN, bool TB>
 __device__ __noinline__ void item_f32(const Desc& d, int tm, int tn, char* lds) {
-  tiles::gemm_f32_tile<BM, BN, kF32BK, false, TB, true>(
-      d.out, d.ldc, reinterpret_cast<const float*>(d.a), d.lda,
-      reinterpret_cast<const float*>(d.b), d.ldb, d.M, d.N, d.K, tm * BM, tn * BN,
-      reinterpret_cast<float*>(lds));
+  const float* A = gptr<const float>(d.a);
+  const float* B = gptr<const float>(d.b);
+  float* C = gptr<float>(d.out);
+  if (tiles::f32_async_eligible(A, d.lda, B, d.ldb, d.M, d.N, d.K, false, TB))
+    tiles::gemm_f32_async_tile<BM, BN, kF32Stages, false, TB>(
+        C, d.ldc, A, d.lda, B, d.ldb, d.M, d.N, d.K, tm * BM, tn * BN,
+        reinterpret_cast<f32x4*>(lds));
+  else
+    tiles::gemm_f32_tile<BM, BN, kF32BK, false, TB, true>(C, d.ldc, A, d.lda, B, d.ldb, d.M, d.N,
+                                                          d.K, tm * BM, tn * BN,
+                                                          reinterpret_cast<float*>(lds));
 }
 template <int BM, int BN, bool TB>
 __device__ __noinline__ void item_bf16(const Desc& d, int tm, int tn, char* lds) {
-  tiles::gemm_bf16_tile<BM, BN, 32, TB>(d.out, d.ldc, reinterpret_cast<const uint16_t*>(d.a),
-                                        d.lda, reinterpret_cast<const uint16_t*>(d.b), d.ldb, d.M,
-                                        d.N, d.K, tm * BM, tn * BN, reinterpret_cast<i32x4*>(lds));
+  tiles::gemm_bf16_tile<BM, BN, 32, TB>(gptr<float>(d.out), d.ldc, gptr<const uint16_t>(d.a),
+                                        d.lda, gptr<const uint16_t>(d.b), d.ldb, d.M, d.N, d.K,
+                                        tm * BM, tn * BN, reinterpret_cast<i32x4*>(lds));
 }
 __device__ __forceinline__ void run_gemm_item(const Desc& d, int tile, char* lds) {
   const int tm = tile / d.tiles_n, tn = tile - tm * d.tiles_n;
@@ -159,8 +178,8 @@ __global__ __launch_bounds__(kThreads, stencil_occupancy(K)) void batched_stenci
     const Desc& d = descs[desc];
     const int tm = tile / d.tiles_n, tn = tile - tm * d.tiles_n;
     tiles::stencil_lds_tile<K, VEC, TY, true, true>(
-        d.out, d.ldc, reinterpret_cast<const float*>(d.a), d.lda, d.M, d.N,
-        reinterpret_cast<const float*>(d.b), d.zero_pad, tm * TY, tn * tiles::kStencilTX, lds);
+        gptr<float>(d.out), d.ldc, gptr<const float>(d.a), d.lda, d.M, d.N, gptr<const float>(d.b),
+        d.zero_pad, tm * TY, tn * tiles::kStencilTX, lds);
     __syncthreads();  // every wave is done with the LDS tile before the next item fills it
   }
 }
@@ -377,8 +396,8 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
                                     forced_kind);
     plan->kinds.push_back(kind);
     const KindShape& s = kShape[kind];
-    Desc d{p.C, p.A, p.B, p.lda, p.ldb, p.ldc, (int)p.M, (int)p.N, (int)p.K, kind,
-           ceil_div(p.N, s.bn), 0, 0};
+    Desc d{(uint64_t)(uintptr_t)p.C, (uint64_t)(uintptr_t)p.A, (uint64_t)(uintptr_t)p.B, p.lda,
+           p.ldb, p.ldc, (int)p.M, (int)p.N, (int)p.K, kind, ceil_div(p.N, s.bn), 0, 0};
     descs.push_back(d);
     ntile.push_back((p.M == 0 || p.N == 0) ? 0 : ceil_div(p.M, s.bm) * d.tiles_n);
     unit.push_back(cost[kind].a + cost[kind].b * p.K);
@@ -389,7 +408,8 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
     const int kind = forced_kind >= STENCIL_1 ? forced_kind
                                               : (vec ? STENCIL_1 : STENCIL_1S) + (p.k - 1) / 2;
     plan->kinds.push_back(kind);
-    Desc d{p.out, p.in, p.w, p.ld_in, 0, p.ld_out, (int)p.H, (int)p.W, p.k, kind,
+    Desc d{(uint64_t)(uintptr_t)p.out, (uint64_t)(uintptr_t)p.in, (uint64_t)(uintptr_t)p.w,
+           p.ld_in, 0, p.ld_out, (int)p.H, (int)p.W, p.k, kind,
            ceil_div(p.W, tiles::kStencilTX), p.pad == RISE_PAD_ZERO, 0};
     descs.push_back(d);
     ntile.push_back((p.H == 0 || p.W == 0) ? 0 : ceil_div(p.H, kShape[kind].bm) * d.tiles_n);

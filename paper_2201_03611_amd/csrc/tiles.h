@@ -4,6 +4,7 @@
 // that runs several kinds of tiles can overlay them in one buffer.
 #pragma once
 
+#include "async_copy.h"
 #include "common.h"
 
 namespace rise {
@@ -189,6 +190,167 @@ __device__ __forceinline__ void gemm_f32_tile(float* __restrict__ C, int64_t ldc
       for (int r = 0; r < 16; r++) {
         const int row = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * kl + (r & 3);
         if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// ===========================================================================
+// FP32 GEMM tile, asynchronous-ring schedule.
+// Each operand's slab (16 values of k by BM or BN values of m or n) is staged
+// in the orientation it is stored in, so every 16-byte chunk goes from global
+// memory to LDS unchanged (global_load_lds: lane i's 16 bytes land at the
+// wave-uniform base + 16 i; the swizzle below is applied on the global side by
+// choosing which chunk each lane fetches):
+//   rows along k (A as stored, B read through transpose): MN rows of 4 chunks;
+//     chunk p of row r holds logical chunk p ^ ((r >> 2) & 3), so the 16 rows
+//     one 16-lane group reads at one logical chunk fall in 16 distinct 16-byte
+//     slots of a 256-byte (64-bank) LDS line;
+//   rows along m or n (A read through transpose, B as stored): 16 rows of MN/4
+//     chunks; chunk p of row k holds logical chunk p ^ (8 ((k >> 3) & 1)), so
+//     rows k and k + 8, which the two halves of a wave read together, use
+//     different banks.
+// The 32x32x2 MFMA's k pair is (k, k + 8) at step t = 0..7 of a slab (lane
+// half kl supplies k = 8 kl + t): the sum over a slab is the same, and a lane
+// of a rows-along-k operand then reads its values of four steps with one
+// 16-byte LDS read.
+// Ragged M and N: rows (chunks) past the edge are fetched from the last valid
+// row (chunk) and only feed outputs that are not stored.  K is a whole number
+// of slabs (checked by the launcher), so no k beyond K is ever added.
+template <int MN, bool ALONG_K>
+struct AsyncSlab {
+  static constexpr int CHUNKS = MN * 4;  // 16-byte chunks of a 16 x MN slab
+  // source of slab chunk `idx` for slab 0, and the advance per slab
+  __device__ static const float* src(const float* X, int64_t ld, int mn0, int mn_total, int idx,
+                                     int64_t& step) {
+    if (ALONG_K) {
+      const int r = idx >> 2, c = (idx & 3) ^ ((r >> 2) & 3);
+      const int row = min(mn0 + r, mn_total - 1);
+      step = 16;
+      return X + (int64_t)row * ld + 4 * c;
+    }
+    const int k = idx / (MN / 4), c = (idx % (MN / 4)) ^ (8 * ((k >> 3) & 1));
+    const int col = min(mn0 + 4 * c, mn_total - 4);
+    step = 16 * ld;
+    return X + (int64_t)k * ld + col;
+  }
+  // values at k = 8 kl + 4 h + s (s = 0..3) of row/column r of the slab
+  __device__ static f32x4 frag(const f32x4* slab, int r, int kl, int h) {
+    if (ALONG_K) return slab[r * 4 + ((2 * kl + h) ^ ((r >> 2) & 3))];
+    const float* f = reinterpret_cast<const float*>(slab);
+    f32x4 v;
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      const int k = 8 * kl + 4 * h + s;
+      v[s] = f[k * MN + 4 * ((r >> 2) ^ (8 * ((k >> 3) & 1))) + (r & 3)];
+    }
+    return v;
+  }
+};
+
+template <int BM, int BN, int STAGES>
+struct F32AsyncCfg {
+  static constexpr int SL = BM * 4 + BN * 4;   // chunks per ring stage: A slab, then B slab
+  static constexpr int LDS_CHUNKS = STAGES * SL;
+};
+
+// The operands' storage allows the asynchronous ring: 16-byte chunks and
+// whole slabs of 16 k (K > 0, K % 16 == 0, 16-byte aligned rows, and the rows
+// along m or n whole chunks).
+__host__ __device__ inline bool f32_async_eligible(const float* A, int64_t lda, const float* B,
+                                                   int64_t ldb, int M, int N, int K, bool ta,
+                                                   bool tb) {
+  return K > 0 && K % 16 == 0 && M > 0 && N > 0 && ((uintptr_t)A & 15) == 0 &&
+         ((uintptr_t)B & 15) == 0 && lda % 4 == 0 && ldb % 4 == 0 && (!ta || M % 4 == 0) &&
+         (tb || N % 4 == 0);
+}
+
+// C[m0:m0+BM, n0:n0+BN] = A B with the whole 256-thread workgroup (2 x 2
+// waves); lds holds F32AsyncCfg::LDS_CHUNKS 16-byte chunks.  No copy is in
+// flight into lds when it returns.
+template <int BM, int BN, int STAGES, bool TA, bool TB>
+__device__ __forceinline__ void gemm_f32_async_tile(float* __restrict__ C, int64_t ldc,
+                                                    const float* __restrict__ A, int64_t lda,
+                                                    const float* __restrict__ B, int64_t ldb,
+                                                    int M, int N, int K, int m0, int n0,
+                                                    f32x4* lds_base) {
+  using SA = AsyncSlab<BM, !TA>;
+  using SB = AsyncSlab<BN, TB>;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
+  constexpr int SL = F32AsyncCfg<BM, BN, STAGES>::SL;
+  constexpr int NCP = SL / kThreads;           // copies per thread per slab
+  static_assert(SL % kThreads == 0 && SA::CHUNKS % 64 == 0, "a copy is all A or all B");
+  static_assert(STAGES >= 3, "ring of at least three slabs");
+  static_assert(TM >= 1 && TN >= 1 && BM >= 64 && BN >= 64, "tile of at least 64 x 64");
+  auto lds = reinterpret_cast<f32x4(*)[SL]>(lds_base);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+
+  const float* src[NCP];
+  int64_t step[NCP];
+#pragma unroll
+  for (int j = 0; j < NCP; j++) {
+    const int slot = (wave * NCP + j) * 64 + lane;
+    src[j] = slot < SA::CHUNKS ? SA::src(A, lda, m0, M, slot, step[j])
+                               : SB::src(B, ldb, n0, N, slot - SA::CHUNKS, step[j]);
+  }
+  const int nk = K / 16;
+  auto issue = [&](int kt) {  // slab min(kt, nk - 1) -> ring stage kt % STAGES
+    const int64_t kk = kt < nk ? kt : nk - 1;
+    const int buf = kt % STAGES;
+#pragma unroll
+    for (int j = 0; j < NCP; j++) async::copy16(src[j] + kk * step[j], &lds[buf][(wave * NCP + j) * 64]);
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  const int kl = lane >> 5, il = lane & 31;
+#pragma unroll
+  for (int st = 0; st < STAGES - 1; st++) issue(st);
+  for (int kt = 0; kt < nk; kt++) {
+    const int buf = kt % STAGES;
+    async::wait_vmcnt<(STAGES - 2) * NCP>();  // this wave's copies of slab kt have landed
+    async::wait_lgkmcnt0();                   // and its reads of slab kt - 1 are done
+    async::barrier();                         // so every copy of slab kt is visible and
+    issue(kt + STAGES - 1);                   // the stage of slab kt - 1 can be refilled
+    const f32x4* As = &lds[buf][0];
+    const f32x4* Bs = &lds[buf][SA::CHUNKS];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      f32x4 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; i++) a[i] = SA::frag(As, wm0 + 32 * i + il, kl, h);
+#pragma unroll
+      for (int j = 0; j < TN; j++) b[j] = SB::frag(Bs, wn0 + 32 * j + il, kl, h);
+#pragma unroll
+      for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+#pragma unroll
+          for (int j = 0; j < TN; j++)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+    }
+  }
+  async::wait_vmcnt<0>();  // the clamped copies past the last slab land before the exit
+
+  // join . join: D layout of a 32x32 block, lane l holds column l % 32 and rows
+  // 8 (r / 4) + 4 (l / 32) + r % 4; stores guarded on edge tiles only
+  const bool full = m0 + BM <= M && n0 + BN <= N;
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+      const int col = n0 + wn0 + j * 32 + il;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * kl + (r & 3);
+        if (full || (row < M && col < N)) C[(int64_t)row * ldc + col] = acc[i][j][r];
       }
     }
 }

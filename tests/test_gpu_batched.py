@@ -147,6 +147,27 @@ def test_small_mixed_batch_and_graph_replays(rise):
     plan.destroy()
 
 
+def test_f32_tiles_both_schedules(rise):
+    # K a multiple of 16 takes the asynchronous-ring tile, any other K the
+    # register-staged one (zero-filled k past K); both in one plan, both opB
+    import torch
+
+    g = ri.rng(31)
+    sizes = [(96, 160, 64), (200, 72, 44), (128, 128, 100), (64, 96, 20), (136, 264, 48)]
+    gemms = []
+    for i, (M, N, K) in enumerate(sizes * 2):
+        gemms.append(dict(M=M, N=N, K=K, opB=i % 2, A=ri.uniform_matrix(g, M, K),
+                          B=ri.uniform_matrix(g, K, N), bf16=False))
+    gp, sp, keep = to_device(rise, gemms, [])
+    print(f"batch: {len(gemms)} f32 gemms, K in {sorted(set(s[2] for s in sizes))}", flush=True)
+    plan = rise.Plan(gp, len(gemms), sp, 0)
+    plan.launch()
+    torch.cuda.synchronize()
+    for p in gemms:
+        check_gemm(p, host(p["dC"]))
+    plan.destroy()
+
+
 def test_batched_equals_single_calls(rise):
     import torch
 
