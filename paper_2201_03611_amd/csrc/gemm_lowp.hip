@@ -542,7 +542,7 @@ const TileRow kTiles[] = {
     {RISE_MODE_BF16, {256, 256, 32}},   {RISE_MODE_BF16X3, {256, 256, 16}},
     {RISE_MODE_BF16X3, {256, 256, 32}}, {RISE_MODE_BF16X3, {128, 128, 32}},
     {RISE_MODE_BF16X6, {256, 256, 16}}, {RISE_MODE_BF16X6, {128, 128, 16}},
-    {RISE_MODE_FP8, {256, 256, 128}},   {RISE_MODE_FP8, {128, 128, 128}},
+    {RISE_MODE_FP8, {128, 128, 128}},
 };
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -600,7 +600,8 @@ bool gemm_lowp_tile_supported(rise_mode mode, const rise_tile& t) {
 }
 
 rise_tile gemm_lowp_default_tile(rise_mode mode, int M, int N, int K) {
-  // FP8: the 128 x 128 tile (the 256 x 256 one runs out of registers);
+  // FP8: the 128 x 128 tile (a 256 x 256 FP8 tile needs more registers than a
+  // wave has and spills);
   // bf16 modes: 256 x 256 when it still gives every CU a tile, else 128 x 128
   // (measured at 8192^3: bf16 1.14 vs 1.23 ms, bf16x3 3.09 vs 3.22 ms)
   const int bk = mode == RISE_MODE_BF16 ? 64 : mode == RISE_MODE_BF16X3 ? 32
@@ -629,7 +630,6 @@ rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStrea
       if (t.bm == 256) return launch_bf16<256, 256, 16, RISE_MODE_BF16X6>(g, s);
       return launch_bf16<128, 128, 16, RISE_MODE_BF16X6>(g, s);
     case RISE_MODE_FP8:
-      if (t.bm == 256) return launch_fp8<256, 256>(g, s);
       return launch_fp8<128, 128>(g, s);
     default:
       return fail(RISE_ERR_UNSUPPORTED, "packed gemm: mode");

@@ -259,6 +259,44 @@ __global__ __launch_bounds__(kThreads) void prep_stream_kernel(
   }
 }
 
+// The same for FP8 (k_out a multiple of 32, so a 32-element scale block is the
+// 8-value chunks of 4 consecutive lanes of one row): the block's amax is
+// combined across those lanes, each lane stores its 8 codes, the block's first
+// lane its scale byte.
+__global__ __launch_bounds__(kThreads) void prep_stream_fp8_kernel(
+    uint8_t* __restrict__ out, int64_t rows_out, int64_t k_out, const float* __restrict__ src,
+    int64_t rows, int64_t K, int64_t ld_r) {
+  const int64_t chunks = k_out / 8;  // a multiple of 4
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= rows_out * chunks) return;  // whole 4-lane blocks leave together
+  const int64_t gr = t / chunks, gk = (t - gr * chunks) * 8;
+  float x[8];
+  if (gr < rows && gk + 8 <= K) {
+    const f32x4* q = reinterpret_cast<const f32x4*>(src + gr * ld_r + gk);
+    const f32x4 v0 = q[0], v1 = q[1];
+    x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
+    x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; e++) x[e] = (gr < rows && gk + e < K) ? src[gr * ld_r + gk + e] : 0.f;
+  }
+  float amax = 0.f;
+#pragma unroll
+  for (int e = 0; e < 8; e++) amax = fmaxf(amax, fabsf(x[e]));
+  amax = fmaxf(amax, __shfl_xor(amax, 1));
+  amax = fmaxf(amax, __shfl_xor(amax, 2));
+  const int ex = e4m3_block_exp(amax);
+  const float sc = __uint_as_float((uint32_t)(127 + ex) << 23);  // 2^ex, ex >= -120
+  uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    w0 |= (uint32_t)e4m3_rne(x[e] * sc) << (8 * e);
+    w1 |= (uint32_t)e4m3_rne(x[4 + e] * sc) << (8 * e);
+  }
+  *reinterpret_cast<uint2*>(out + gr * k_out + gk) = uint2{w0, w1};
+  if ((gk & 31) == 0) out[rows_out * k_out + gr * (k_out / 32) + gk / 32] = (uint8_t)(127 - ex);
+}
+
 template <typename SRC, int MODE>
 rise_status launch_mode(const PrepArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.rows_out + TR - 1) / TR), (unsigned)((a.k_out + TK - 1) / TK));
@@ -278,6 +316,13 @@ rise_status launch_mode(const PrepArgs& a, hipStream_t s) {
                        block, 0, s, a.out, a.rows_out, a.k_out, reinterpret_cast<const float*>(a.src),
                        a.rows, a.K, a.ld_r, vec_out);
     return check_launch("prep_stream_kernel");
+  }
+  if (layout == 1 && MODE == RISE_MODE_FP8 && vec_out && a.k_out % 32 == 0) {
+    const int64_t threads = a.rows_out * (a.k_out / 8);
+    hipLaunchKernelGGL(prep_stream_fp8_kernel, dim3((unsigned)((threads + kThreads - 1) / kThreads)),
+                       block, 0, s, reinterpret_cast<uint8_t*>(a.out), a.rows_out, a.k_out,
+                       reinterpret_cast<const float*>(a.src), a.rows, a.K, a.ld_r);
+    return check_launch("prep_stream_fp8_kernel");
   }
   if (layout == 1)
     hipLaunchKernelGGL((prep_kernel<SRC, MODE, 1>), grid, block, 0, s, a.out, a.rows_out, a.k_out,

@@ -196,7 +196,7 @@ def test_tiles_and_workspace_queries(lib):
 
     for mode in range(5):
         n = lib.rise_gemm_tiles(mode, None, 0)
-        assert n >= 2
+        assert n >= (1 if mode == 4 else 2)  # FP8: the 128 x 128 tile only
         arr = (RiseTile * n)()
         assert lib.rise_gemm_tiles(mode, arr, n) == n
         for t in arr:
