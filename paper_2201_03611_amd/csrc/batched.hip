@@ -321,20 +321,12 @@ struct Launch {
   int cls, first, count, grid;
 };
 
-// Concurrent classes: the stencil kernels run on a second stream of the plan
-// (forked from and joined back to the launch stream, default priority) while
-// the GEMM kernel, one workgroup per CU, leaves room on every CU for stencil
-// workgroups; the matrix-core-bound and HBM-bound tiles then overlap.
-constexpr bool kConcurrentClasses = false;
-
 struct PlanImpl {
   Desc* d_desc = nullptr;
   Item* d_items = nullptr;
   int* d_counter = nullptr;
   int n_items = 0;
   std::vector<Launch> launches;
-  hipStream_t aux = nullptr;  // the stencil kernels' stream (kConcurrentClasses)
-  hipEvent_t fork = nullptr, join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<int> kinds;  // chosen kind per problem (GEMMs first, then stencils)
@@ -347,9 +339,6 @@ namespace {
 hipError_t enqueue(const PlanImpl* p, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, p->d_counter);
   hipError_t e = hipGetLastError();
-  const bool fork = p->aux != nullptr;
-  if (fork && e == hipSuccess) e = hipEventRecord(p->fork, s);
-  if (fork && e == hipSuccess) e = hipStreamWaitEvent(p->aux, p->fork, 0);
   for (const Launch& l : p->launches) {
     if (e != hipSuccess) break;
     const Item* items = p->d_items + l.first;
@@ -359,12 +348,9 @@ hipError_t enqueue(const PlanImpl* p, hipStream_t s) {
       e = hipGetLastError();
     } else {
       void* args[] = {(void*)&p->d_desc, (void*)&items, (void*)&l.count};
-      e = hipLaunchKernel(stencil_class_kernel(l.cls), dim3(l.grid), dim3(kThreads), args, 0,
-                          fork ? p->aux : s);
+      e = hipLaunchKernel(stencil_class_kernel(l.cls), dim3(l.grid), dim3(kThreads), args, 0, s);
     }
   }
-  if (fork && e == hipSuccess) e = hipEventRecord(p->join, p->aux);
-  if (fork && e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
   return e;
 }
 }  // namespace
@@ -443,13 +429,9 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 256;
-  bool any_stencil = false;
-  for (int c = 0; c < kStencilClasses; c++) any_stencil |= stencil_count[c] > 0;
-  const bool concurrent = kConcurrentClasses && n_gemm_items > 0 && any_stencil;
-  const int gemm_per_cu = concurrent ? 1 : kGemmOccupancy;
   if (n_gemm_items > 0)
     plan->launches.push_back(
-        Launch{-1, 0, n_gemm_items, std::max(1, std::min(n_gemm_items, gemm_per_cu * cus))});
+        Launch{-1, 0, n_gemm_items, std::max(1, std::min(n_gemm_items, kGemmOccupancy * cus))});
   for (int c = 0; c < kStencilClasses; c++) {
     if (stencil_count[c] == 0) continue;
     int per_cu = 0;
@@ -475,14 +457,6 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
        (e = hipMemcpy(plan->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)) {
     rise_plan_free(plan);
     return fail(RISE_ERR_HIP, std::string("rise_plan_create: ") + hipGetErrorString(e));
-  }
-  if (concurrent) {
-    if ((e = hipStreamCreateWithFlags(&plan->aux, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&plan->fork, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&plan->join, hipEventDisableTiming)) != hipSuccess) {
-      rise_plan_free(plan);
-      return fail(RISE_ERR_HIP, std::string("rise_plan_create: ") + hipGetErrorString(e));
-    }
   }
   // capture the plan's kernels on a private stream
   hipStream_t cap;
@@ -527,9 +501,6 @@ void rise_plan_free(PlanImpl* p) {
   if (p->d_desc) (void)hipFree(p->d_desc);
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_counter) (void)hipFree(p->d_counter);
-  if (p->fork) (void)hipEventDestroy(p->fork);
-  if (p->join) (void)hipEventDestroy(p->join);
-  if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
 }
 

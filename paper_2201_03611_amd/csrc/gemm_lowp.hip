@@ -395,6 +395,12 @@ __device__ __forceinline__ void copy16_to_lds(const void* src, void* lds_base) {
   __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
 #endif
 }
+// 4 bytes per lane, global -> LDS at lds_base + 4 * lane
+__device__ __forceinline__ void copy4_to_lds(const void* src, void* lds_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, lds_base, 4, 0, 0);
+#endif
+}
 
 template <int BM, int BN, int BK, int STAGES, int MODE, bool XPF>
 __global__ __launch_bounds__(kThreads, 1) void packed_bf16_async_kernel(
@@ -533,6 +539,182 @@ __global__ __launch_bounds__(kThreads, 1) void packed_bf16_async_kernel(
   store_tile<TM, TN>(C, ldc, M, N, m0 + wm0, n0 + wn0, lane, acc);
 }
 
+// ---------------------------------------------------------------------------
+// FP8 kernel with asynchronous slab copies, for 256 x 256 tiles.  The register
+// staging of packed_fp8_kernel does not fit beside the 256 accumulator
+// registers of a 256 x 256 tile, so the slabs (E4M3 codes of A and B rows,
+// then the four E8M0 scale bytes of each row packed in one word) go from
+// global memory straight into a two-buffer LDS ring.  The tile halves the
+// global and LDS bytes per flop of the 128 x 128 tile.
+//
+// Schedule of slab kt (two scaled k-steps of 64) in each wave:
+//   read the k-step-1 fragments of slab kt      | k-step-0 MFMAs of slab kt
+//   wait: own copies of slab kt+1 landed, own reads done; barrier
+//   copy slab kt+2 into the buffer of slab kt (every wave is past its reads)
+//   read the k-step-0 fragments of slab kt+1    | k-step-1 MFMAs of slab kt
+// so fragment reads run under MFMAs, and a copy has one slab of MFMA time to
+// land.  Each slab also touches one dword of every 128-byte line that the
+// tile reads three slabs later (into a dummy LDS word per lane), which pulls
+// those lines into L2 before their copies are issued; a tile touches half of
+// its rows, the tile next to it in n (for A rows) or m (for B rows) the other
+// half.  Codes and scales share one LDS array: the compiler then adds no wait
+// for the copies in flight in front of the fragment reads.
+__device__ __forceinline__ void wait_lgkmcnt0_visible() {
+  // s_waitcnt lgkmcnt(0) (vmcnt and expcnt fields at their maxima) as an
+  // instruction the compiler's own wait insertion accounts for
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(kThreads, 1) void packed_fp8_async_kernel(
+    float* __restrict__ C, int64_t ldc, const uint8_t* __restrict__ Ap,
+    const uint8_t* __restrict__ Bp, int M, int N, int Kp, int Mp, int Np, int tiles_m,
+    int tiles_n) {
+  constexpr int BK = 128, CH = BK / 16;
+  constexpr int ROWS = BM + BN;
+  constexpr int CODE_SLOTS = ROWS * CH;       // 16-byte chunks of one buffer
+  constexpr int NCP = CODE_SLOTS / kThreads;  // code copies per thread per slab
+  constexpr int NSW = ROWS / 64;              // wave-wide scale copies per slab
+  constexpr int NSC = (NSW + 3) / 4;          // per wave (the last one guarded)
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
+  constexpr int PF = 3;                       // L2 touch distance in slabs
+  static_assert(BM == 256 && BN == 256, "the L2 touch covers 4 x 64 rows of A and of B");
+  static_assert(CODE_SLOTS % kThreads == 0, "slab shape");
+
+  __shared__ i32x4 lds[2 * CODE_SLOTS + ROWS / 2 + 64];
+  i32x4* const codes = lds;
+  uint32_t* const scales = reinterpret_cast<uint32_t*>(lds + 2 * CODE_SLOTS);
+  i32x4* const dummy = lds + 2 * CODE_SLOTS + ROWS / 2 + (threadIdx.x >> 6) * 16;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+  int tm, tn;
+  grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, 2, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int sstride = Kp / 32;
+
+  // code copy q of this lane fills slot (wave * NCP + q) * 64 + lane: row
+  // slot / CH, physical chunk slot % CH, which holds the logical chunk given
+  // by the swizzle's inverse
+  const uint8_t* csrc[NCP];
+#pragma unroll
+  for (int q = 0; q < NCP; q++) {
+    const int slot = (wave * NCP + q) * 64 + lane;
+    const int r = slot / CH, pc = slot % CH;
+    const int c = pc ^ ((r / (16 / CH)) % CH);
+    csrc[q] = r < BM ? Ap + (int64_t)(m0 + r) * Kp + c * 16
+                     : Bp + (int64_t)(n0 + r - BM) * Kp + c * 16;
+  }
+  // scale copy q of this wave: the words of rows (wave + 4 q) * 64 + lane
+  const uint8_t* ssrc[NSC];
+#pragma unroll
+  for (int q = 0; q < NSC; q++) {
+    const int r = ((wave + 4 * q) % NSW) * 64 + lane;
+    ssrc[q] = r < BM ? Ap + (int64_t)Mp * Kp + (int64_t)(m0 + r) * sstride
+                     : Bp + (int64_t)Np * Kp + (int64_t)(n0 + r - BM) * sstride;
+  }
+  // L2 touch row of this lane: waves 0, 1 take A rows, waves 2, 3 B rows
+  const uint8_t* const tsrc =
+      wave < 2 ? Ap + (int64_t)(m0 + (wave + 2 * (tn & 1)) * 64 + lane) * Kp
+               : Bp + (int64_t)(n0 + (wave - 2 + 2 * (tm & 1)) * 64 + lane) * Kp;
+
+  const int nk = Kp / BK;
+  auto issue = [&](int kt) {  // slab min(kt, nk - 1) -> buffer kt % 2
+    const int k = kt < nk ? kt : nk - 1;
+    const int buf = kt & 1;
+#pragma unroll
+    for (int q = 0; q < NCP; q++)
+      copy16_to_lds(csrc[q] + k * BK, codes + buf * CODE_SLOTS + (wave * NCP + q) * 64);
+#pragma unroll
+    for (int q = 0; q < NSC; q++)
+      if (NSW % 4 == 0 || wave + 4 * q < NSW)
+        copy4_to_lds(ssrc[q] + k * (BK / 32), scales + buf * ROWS + (wave + 4 * q) * 64);
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+  // fragment sets: set s holds k-step s of a slab, with the raw scale words
+  // (the byte is taken where the MFMAs use it, after the reads have landed)
+  const int il = lane & 31, kh = lane >> 5;
+  i32x8 fa[2][TM], fb[2][TN];
+  uint32_t wa[2][TM], wb[2][TN];
+  auto reads = [&](int buf, int set) {
+    // the same operand and scale layout as packed_fp8_kernel
+    const int c0 = 4 * set + kh, c1 = 4 * set + 2 + kh;
+    const i32x4* cb = codes + buf * CODE_SLOTS;
+    const uint32_t* sc = scales + buf * ROWS;
+#pragma unroll
+    for (int i = 0; i < TM; i++) {
+      const int r = wm0 + 32 * i + il;
+      const i32x4 lo = cb[swz<CH>(r, c0)], hi = cb[swz<CH>(r, c1)];
+      fa[set][i] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      wa[set][i] = sc[r];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+      const int r = BM + wn0 + 32 * j + il;
+      const i32x4 lo = cb[swz<CH>(r, c0)], hi = cb[swz<CH>(r, c1)];
+      fb[set][j] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      wb[set][j] = sc[r];
+    }
+  };
+  auto mfmas = [&](int set) {
+    const int sh = 8 * (2 * set + kh);
+    int xa[TM], xb[TN];
+#pragma unroll
+    for (int i = 0; i < TM; i++) xa[i] = (int)((wa[set][i] >> sh) & 0xffu);
+#pragma unroll
+    for (int j = 0; j < TN; j++) xb[j] = (int)((wb[set][j] >> sh) & 0xffu);
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+      for (int j = 0; j < TN; j++)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[set][i], fb[set][j],
+                                                                   acc[i][j], 0, 0, 0, xa[i], 0,
+                                                                   xb[j]);
+  };
+
+  if (nk > 0) {
+    issue(0);
+    wait_vmcnt<0>();
+    __builtin_amdgcn_sched_barrier(0);
+    raw_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    issue(1);
+    reads(0, 0);
+  }
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    wait_lgkmcnt0_visible();  // set 0, read a whole MFMA block ago, has landed
+    reads(cur, 1);
+    copy4_to_lds(tsrc + (kt + PF < nk ? kt + PF : nk - 1) * BK, dummy);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(0);
+    __builtin_amdgcn_sched_barrier(0);
+    wait_vmcnt<1>();          // this wave's copies of slab kt + 1 have landed (the
+                              // L2 touch just issued may still be out)
+    wait_lgkmcnt0_visible();  // and its reads of slab kt are done
+    __builtin_amdgcn_sched_barrier(0);
+    raw_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    issue(kt + 2);            // refills the buffer of slab kt
+    reads(cur ^ 1, 0);        // slab kt + 1 (past the end: a clamped copy, unused)
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  wait_vmcnt<0>();  // the clamped tail copies land before the workgroup ends
+  wait_lgkmcnt0_visible();
+
+  store_tile<TM, TN>(C, ldc, M, N, m0 + wm0, n0 + wn0, lane, acc);
+}
+
 struct TileRow {
   rise_mode mode;
   rise_tile t;
@@ -542,7 +724,7 @@ const TileRow kTiles[] = {
     {RISE_MODE_BF16, {256, 256, 32}},   {RISE_MODE_BF16X3, {256, 256, 16}},
     {RISE_MODE_BF16X3, {256, 256, 32}}, {RISE_MODE_BF16X3, {128, 128, 32}},
     {RISE_MODE_BF16X6, {256, 256, 16}}, {RISE_MODE_BF16X6, {128, 128, 16}},
-    {RISE_MODE_FP8, {128, 128, 128}},
+    {RISE_MODE_FP8, {256, 256, 128}},   {RISE_MODE_FP8, {128, 128, 128}},
 };
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -573,6 +755,15 @@ rise_status launch_bf16_async(const PackedGemm& g, hipStream_t s) {
 }
 
 template <int BM, int BN>
+rise_status launch_fp8_async(const PackedGemm& g, hipStream_t s) {
+  int tiles_m = g.Mp / BM, tiles_n = g.Np / BN;
+  hipLaunchKernelGGL((packed_fp8_async_kernel<BM, BN>), dim3(tiles_m * tiles_n), dim3(kThreads),
+                     0, s, g.C, g.ldc, (const uint8_t*)g.Ap, (const uint8_t*)g.Bp, g.M, g.N, g.Kp,
+                     g.Mp, g.Np, tiles_m, tiles_n);
+  return check_launch("packed_fp8_async_kernel");
+}
+
+template <int BM, int BN>
 rise_status launch_fp8(const PackedGemm& g, hipStream_t s) {
   int tiles_m = g.Mp / BM, tiles_n = g.Np / BN;
   hipLaunchKernelGGL((packed_fp8_kernel<BM, BN>), dim3(tiles_m * tiles_n), dim3(kThreads), 0, s,
@@ -600,13 +791,11 @@ bool gemm_lowp_tile_supported(rise_mode mode, const rise_tile& t) {
 }
 
 rise_tile gemm_lowp_default_tile(rise_mode mode, int M, int N, int K) {
-  // FP8: the 128 x 128 tile (a 256 x 256 FP8 tile needs more registers than a
-  // wave has and spills);
-  // bf16 modes: 256 x 256 when it still gives every CU a tile, else 128 x 128
-  // (measured at 8192^3: bf16 1.14 vs 1.23 ms, bf16x3 3.09 vs 3.22 ms)
+  // 256 x 256 when it still gives every CU a tile, else 128 x 128 (measured
+  // at 8192^3: bf16 1.14 vs 1.23 ms, bf16x3 3.09 vs 3.22 ms, fp8 with the
+  // asynchronous kernel 0.52-0.61 vs 0.71-0.80 ms)
   const int bk = mode == RISE_MODE_BF16 ? 64 : mode == RISE_MODE_BF16X3 ? 32
                : mode == RISE_MODE_BF16X6 ? 16 : 128;
-  if (mode == RISE_MODE_FP8) return rise_tile{128, 128, bk};
   long tiles_big = (long)((M + 255) / 256) * ((N + 255) / 256);
   return tiles_big >= 256 ? rise_tile{256, 256, bk} : rise_tile{128, 128, bk};
 }
@@ -630,6 +819,7 @@ rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStrea
       if (t.bm == 256) return launch_bf16<256, 256, 16, RISE_MODE_BF16X6>(g, s);
       return launch_bf16<128, 128, 16, RISE_MODE_BF16X6>(g, s);
     case RISE_MODE_FP8:
+      if (t.bm == 256) return launch_fp8_async<256, 256>(g, s);
       return launch_fp8<128, 128>(g, s);
     default:
       return fail(RISE_ERR_UNSUPPORTED, "packed gemm: mode");
