@@ -14,6 +14,11 @@ struct PrepArgs {
   int64_t rows, K, ld_r, ld_k;
   rise_mode mode;
   bool src_bf16 = false;
+  // 0: each part is rows_out x k_out, K contiguous.  kblock > 0 (a multiple of
+  // 32 dividing k_out): K-blocked, K block b of row r holds kblock consecutive
+  // elements at (b * rows_out + r) * kblock, so one block of consecutive rows
+  // is contiguous; FP8 scale bytes likewise in groups of kblock / 32.
+  int kblock = 0;
 };
 int prep_parts(rise_mode mode);
 size_t prep_bytes(int64_t rows_out, int64_t k_out, rise_mode mode);
@@ -42,7 +47,8 @@ rise_status launch_gemm_lowp(const GemmLowpArgs& a, const rise_tile& t, void* ws
 
 // Packed operands already prepared in the layout launch_prep writes: A parts
 // Mp x Kp, B parts Np x Kp (B read as transpose(B) rows), Kp a multiple of the
-// tile's bk, Mp and Np multiples of bm and bn.
+// tile's bk, Mp and Np multiples of bm and bn; K-blocked by kblock when
+// packed_kblock(mode, tile) is nonzero.
 struct PackedGemm {
   float* C;
   int64_t ldc;
@@ -50,7 +56,9 @@ struct PackedGemm {
   const void* Bp;
   int M, N, Kp, Mp, Np;
   rise_mode mode;
+  int kblock = 0;
 };
+int packed_kblock(rise_mode mode, const rise_tile& t);
 rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStream_t s);
 
 }  // namespace rise

@@ -20,6 +20,8 @@
 //                                           registers: no extra pass over C.
 #include "gemm_lowp.h"
 
+#include <type_traits>
+
 namespace rise {
 namespace {
 
@@ -540,95 +542,85 @@ __global__ __launch_bounds__(kThreads, 1) void packed_bf16_async_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// FP8 kernel with asynchronous slab copies, for 256 x 256 tiles.  The register
-// staging of packed_fp8_kernel does not fit beside the 256 accumulator
-// registers of a 256 x 256 tile, so the slabs (E4M3 codes of A and B rows,
-// then the four E8M0 scale bytes of each row packed in one word) go from
-// global memory straight into a two-buffer LDS ring.  The tile halves the
-// global and LDS bytes per flop of the 128 x 128 tile.
-//
-// Schedule of slab kt (two scaled k-steps of 64) in each wave:
-//   read the k-step-1 fragments of slab kt      | k-step-0 MFMAs of slab kt
-//   wait: own copies of slab kt+1 landed, own reads done; barrier
-//   copy slab kt+2 into the buffer of slab kt (every wave is past its reads)
-//   read the k-step-0 fragments of slab kt+1    | k-step-1 MFMAs of slab kt
-// so fragment reads run under MFMAs, and a copy has one slab of MFMA time to
-// land.  Each slab also touches one dword of every 128-byte line that the
-// tile reads three slabs later (into a dummy LDS word per lane), which pulls
-// those lines into L2 before their copies are issued; a tile touches half of
-// its rows, the tile next to it in n (for A rows) or m (for B rows) the other
-// half.  Codes and scales share one LDS array: the compiler then adds no wait
-// for the copies in flight in front of the fragment reads.
+// FP8 kernel for 256 x 256 tiles over K-blocked operands (64 codes per block:
+// the 64-byte K slices of consecutive rows are contiguous, and the two scale
+// bytes of a row's slice sit together).  The register staging of
+// packed_fp8_kernel does not fit beside the 256 accumulator registers of a
+// 256 x 256 tile, so each slab (the 64-k slice of the tile's 512 rows, 32 KB,
+// plus 1 KB of scales) goes from global memory straight into LDS with
+// global_load_lds: one copy instruction moves 16 whole rows of 64 bytes, i.e.
+// whole 128-byte lines, which a row-major 64-byte slab would fetch as halves.
+// Slabs flow through a ring of four LDS buffers:
+//   wait for this wave's copies of slab kt+1 and its fragment reads of slab kt;
+//   barrier (slab kt+1 visible; every wave holds slab kt in registers);
+//   copy slab kt+4 into the buffer of slab kt, read slab kt+1's fragments and
+//   run slab kt's 16 MFMAs, the copies and reads interleaved between MFMAs,
+// so a copy has three slabs of MFMA time to land and fragment reads never
+// stall the matrix core.  Codes and scales share one LDS array: the compiler
+// then adds no wait for the copies in flight in front of the fragment reads.
 __device__ __forceinline__ void wait_lgkmcnt0_visible() {
   // s_waitcnt lgkmcnt(0) (vmcnt and expcnt fields at their maxima) as an
   // instruction the compiler's own wait insertion accounts for
   __builtin_amdgcn_s_waitcnt(0xC07F);
 }
 
-template <int BM, int BN>
-__global__ __launch_bounds__(kThreads, 1) void packed_fp8_async_kernel(
+constexpr int kFp8KBlock = 64;
+
+__global__ __launch_bounds__(kThreads, 1) void packed_fp8_kblock_kernel(
     float* __restrict__ C, int64_t ldc, const uint8_t* __restrict__ Ap,
     const uint8_t* __restrict__ Bp, int M, int N, int Kp, int Mp, int Np, int tiles_m,
     int tiles_n) {
-  constexpr int BK = 128, CH = BK / 16;
+  constexpr int BM = 256, BN = 256, KB = kFp8KBlock, CH = KB / 16;
   constexpr int ROWS = BM + BN;
+  constexpr int STAGES = 4;
   constexpr int CODE_SLOTS = ROWS * CH;       // 16-byte chunks of one buffer
-  constexpr int NCP = CODE_SLOTS / kThreads;  // code copies per thread per slab
-  constexpr int NSW = ROWS / 64;              // wave-wide scale copies per slab
-  constexpr int NSC = (NSW + 3) / 4;          // per wave (the last one guarded)
+  constexpr int NCP = CODE_SLOTS / kThreads;  // 8 code copies per thread per slab
+  constexpr int NPS = NCP + 1;                // copies per wave per slab, scales included
+  constexpr int SCW = ROWS * (KB / 32) / 4;   // scale words of one slab
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
-  constexpr int PF = 3;                       // L2 touch distance in slabs
-  static_assert(BM == 256 && BN == 256, "the L2 touch covers 4 x 64 rows of A and of B");
-  static_assert(CODE_SLOTS % kThreads == 0, "slab shape");
+  static_assert(SCW == kThreads, "one scale word per thread");
+  static_assert((STAGES - 1) * NPS < 64, "vmcnt field");
 
-  __shared__ i32x4 lds[2 * CODE_SLOTS + ROWS / 2 + 64];
+  __shared__ i32x4 lds[STAGES * CODE_SLOTS + STAGES * SCW / 4];
   i32x4* const codes = lds;
-  uint32_t* const scales = reinterpret_cast<uint32_t*>(lds + 2 * CODE_SLOTS);
-  i32x4* const dummy = lds + 2 * CODE_SLOTS + ROWS / 2 + (threadIdx.x >> 6) * 16;
+  uint32_t* const scale_words = reinterpret_cast<uint32_t*>(lds + STAGES * CODE_SLOTS);
+  const uint8_t* const scale_bytes = reinterpret_cast<const uint8_t*>(scale_words);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
   int tm, tn;
-  grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, 2, tm, tn);
+  grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, 4, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
-  const int sstride = Kp / 32;
 
-  // code copy q of this lane fills slot (wave * NCP + q) * 64 + lane: row
-  // slot / CH, physical chunk slot % CH, which holds the logical chunk given
-  // by the swizzle's inverse
-  const uint8_t* csrc[NCP];
+  // waves 0, 1 copy the A rows of a slab, waves 2, 3 the B rows; slot
+  // (wave * NCP + q) * 64 + lane of a buffer holds row slot / CH, physical
+  // chunk slot % CH, i.e. the logical chunk given by the swizzle's inverse
+  const bool isB = wave >= 2;
+  const int64_t prows = isB ? Np : Mp;
+  const uint8_t* const plane = isB ? Bp : Ap;
+  const uint8_t* const splane = plane + prows * Kp;
+  const int64_t row0 = isB ? n0 : m0;
+  int coff[NCP];
 #pragma unroll
   for (int q = 0; q < NCP; q++) {
     const int slot = (wave * NCP + q) * 64 + lane;
     const int r = slot / CH, pc = slot % CH;
     const int c = pc ^ ((r / (16 / CH)) % CH);
-    csrc[q] = r < BM ? Ap + (int64_t)(m0 + r) * Kp + c * 16
-                     : Bp + (int64_t)(n0 + r - BM) * Kp + c * 16;
+    coff[q] = (isB ? r - BM : r) * KB + c * 16;
   }
-  // scale copy q of this wave: the words of rows (wave + 4 q) * 64 + lane
-  const uint8_t* ssrc[NSC];
-#pragma unroll
-  for (int q = 0; q < NSC; q++) {
-    const int r = ((wave + 4 * q) % NSW) * 64 + lane;
-    ssrc[q] = r < BM ? Ap + (int64_t)Mp * Kp + (int64_t)(m0 + r) * sstride
-                     : Bp + (int64_t)Np * Kp + (int64_t)(n0 + r - BM) * sstride;
-  }
-  // L2 touch row of this lane: waves 0, 1 take A rows, waves 2, 3 B rows
-  const uint8_t* const tsrc =
-      wave < 2 ? Ap + (int64_t)(m0 + (wave + 2 * (tn & 1)) * 64 + lane) * Kp
-               : Bp + (int64_t)(n0 + (wave - 2 + 2 * (tm & 1)) * 64 + lane) * Kp;
+  // scale word tid of a slab: bytes 4 tid .. 4 tid + 3 of the A rows' pairs
+  // (words 0-127) then the B rows' pairs (words 128-255)
+  const int soff = (isB ? tid - kThreads / 2 : tid) * 4;
 
-  const int nk = Kp / BK;
-  auto issue = [&](int kt) {  // slab min(kt, nk - 1) -> buffer kt % 2
-    const int k = kt < nk ? kt : nk - 1;
-    const int buf = kt & 1;
+  const int nk = Kp / KB;
+  auto issue = [&](int kt) {  // slab min(kt, nk - 1) -> buffer kt % STAGES
+    const int64_t k = kt < nk ? kt : nk - 1;
+    const int buf = kt % STAGES;
+    const uint8_t* cb = plane + (k * prows + row0) * KB;
 #pragma unroll
     for (int q = 0; q < NCP; q++)
-      copy16_to_lds(csrc[q] + k * BK, codes + buf * CODE_SLOTS + (wave * NCP + q) * 64);
-#pragma unroll
-    for (int q = 0; q < NSC; q++)
-      if (NSW % 4 == 0 || wave + 4 * q < NSW)
-        copy4_to_lds(ssrc[q] + k * (BK / 32), scales + buf * ROWS + (wave + 4 * q) * 64);
+      copy16_to_lds(cb + coff[q], codes + buf * CODE_SLOTS + (wave * NCP + q) * 64);
+    copy4_to_lds(splane + (k * prows + row0) * (KB / 32) + soff, scale_words + buf * SCW + wave * 64);
   };
 
   f32x16 acc[TM][TN];
@@ -639,76 +631,71 @@ __global__ __launch_bounds__(kThreads, 1) void packed_fp8_async_kernel(
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
 
-  // fragment sets: set s holds k-step s of a slab, with the raw scale words
-  // (the byte is taken where the MFMAs use it, after the reads have landed)
+  // fragments of one slab (the same operand and scale layout as
+  // packed_fp8_kernel's k-step 0): two register sets, alternating by slab
   const int il = lane & 31, kh = lane >> 5;
   i32x8 fa[2][TM], fb[2][TN];
-  uint32_t wa[2][TM], wb[2][TN];
+  int xa[2][TM], xb[2][TN];
   auto reads = [&](int buf, int set) {
-    // the same operand and scale layout as packed_fp8_kernel
-    const int c0 = 4 * set + kh, c1 = 4 * set + 2 + kh;
     const i32x4* cb = codes + buf * CODE_SLOTS;
-    const uint32_t* sc = scales + buf * ROWS;
+    const uint8_t* sb = scale_bytes + buf * SCW * 4;
 #pragma unroll
     for (int i = 0; i < TM; i++) {
       const int r = wm0 + 32 * i + il;
-      const i32x4 lo = cb[swz<CH>(r, c0)], hi = cb[swz<CH>(r, c1)];
+      const i32x4 lo = cb[swz<CH>(r, kh)], hi = cb[swz<CH>(r, 2 + kh)];
       fa[set][i] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      wa[set][i] = sc[r];
+      xa[set][i] = sb[r * 2 + kh];
     }
 #pragma unroll
     for (int j = 0; j < TN; j++) {
       const int r = BM + wn0 + 32 * j + il;
-      const i32x4 lo = cb[swz<CH>(r, c0)], hi = cb[swz<CH>(r, c1)];
+      const i32x4 lo = cb[swz<CH>(r, kh)], hi = cb[swz<CH>(r, 2 + kh)];
       fb[set][j] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      wb[set][j] = sc[r];
+      xb[set][j] = sb[r * 2 + kh];
     }
   };
-  auto mfmas = [&](int set) {
-    const int sh = 8 * (2 * set + kh);
-    int xa[TM], xb[TN];
-#pragma unroll
-    for (int i = 0; i < TM; i++) xa[i] = (int)((wa[set][i] >> sh) & 0xffu);
-#pragma unroll
-    for (int j = 0; j < TN; j++) xb[j] = (int)((wb[set][j] >> sh) & 0xffu);
+  auto step = [&](int kt, auto set_tag) {
+    constexpr int set = decltype(set_tag)::value;
+    wait_vmcnt<(STAGES - 2) * NPS>();  // this wave's copies of slab kt+1 have landed
+    wait_lgkmcnt0_visible();           // and its fragments of slab kt are in registers
+    __builtin_amdgcn_sched_barrier(0);
+    raw_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    issue(kt + STAGES);                // refills the buffer of slab kt
+    reads((kt + 1) % STAGES, set ^ 1);  // slab kt+1 (past the end: a clamped copy, unused)
 #pragma unroll
     for (int i = 0; i < TM; i++)
 #pragma unroll
       for (int j = 0; j < TN; j++)
         acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[set][i], fb[set][j],
-                                                                   acc[i][j], 0, 0, 0, xa[i], 0,
-                                                                   xb[j]);
+                                                                   acc[i][j], 0, 0, 0,
+                                                                   xa[set][i], 0, xb[set][j]);
+    // one MFMA, then a copy while copies remain, then the fragment reads
+    constexpr int NRD = 3 * (TM + TN);  // two 16-byte reads and a scale byte per fragment
+#pragma unroll
+    for (int t = 0; t < TM * TN; t++) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      if (t < NPS) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, (NRD + TM * TN - 1) / (TM * TN), 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   };
 
   if (nk > 0) {
-    issue(0);
-    wait_vmcnt<0>();
+#pragma unroll
+    for (int st = 0; st < STAGES; st++) issue(st);
+    wait_vmcnt<(STAGES - 1) * NPS>();  // slab 0 has landed
     __builtin_amdgcn_sched_barrier(0);
     raw_barrier();
     __builtin_amdgcn_sched_barrier(0);
-    issue(1);
     reads(0, 0);
   }
-  for (int kt = 0; kt < nk; kt++) {
-    const int cur = kt & 1;
-    wait_lgkmcnt0_visible();  // set 0, read a whole MFMA block ago, has landed
-    reads(cur, 1);
-    copy4_to_lds(tsrc + (kt + PF < nk ? kt + PF : nk - 1) * BK, dummy);
-    __builtin_amdgcn_sched_barrier(0);
-    mfmas(0);
-    __builtin_amdgcn_sched_barrier(0);
-    wait_vmcnt<1>();          // this wave's copies of slab kt + 1 have landed (the
-                              // L2 touch just issued may still be out)
-    wait_lgkmcnt0_visible();  // and its reads of slab kt are done
-    __builtin_amdgcn_sched_barrier(0);
-    raw_barrier();
-    __builtin_amdgcn_sched_barrier(0);
-    issue(kt + 2);            // refills the buffer of slab kt
-    reads(cur ^ 1, 0);        // slab kt + 1 (past the end: a clamped copy, unused)
-    __builtin_amdgcn_sched_barrier(0);
-    mfmas(1);
-    __builtin_amdgcn_sched_barrier(0);
+  int kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    step(kt, std::integral_constant<int, 0>{});
+    step(kt + 1, std::integral_constant<int, 1>{});
   }
+  if (kt < nk) step(kt, std::integral_constant<int, 0>{});
   wait_vmcnt<0>();  // the clamped tail copies land before the workgroup ends
   wait_lgkmcnt0_visible();
 
@@ -754,13 +741,12 @@ rise_status launch_bf16_async(const PackedGemm& g, hipStream_t s) {
   return check_launch("packed_bf16_async_kernel");
 }
 
-template <int BM, int BN>
-rise_status launch_fp8_async(const PackedGemm& g, hipStream_t s) {
-  int tiles_m = g.Mp / BM, tiles_n = g.Np / BN;
-  hipLaunchKernelGGL((packed_fp8_async_kernel<BM, BN>), dim3(tiles_m * tiles_n), dim3(kThreads),
-                     0, s, g.C, g.ldc, (const uint8_t*)g.Ap, (const uint8_t*)g.Bp, g.M, g.N, g.Kp,
-                     g.Mp, g.Np, tiles_m, tiles_n);
-  return check_launch("packed_fp8_async_kernel");
+rise_status launch_fp8_kblock(const PackedGemm& g, hipStream_t s) {
+  int tiles_m = g.Mp / 256, tiles_n = g.Np / 256;
+  hipLaunchKernelGGL(packed_fp8_kblock_kernel, dim3(tiles_m * tiles_n), dim3(kThreads), 0, s,
+                     g.C, g.ldc, (const uint8_t*)g.Ap, (const uint8_t*)g.Bp, g.M, g.N, g.Kp, g.Mp,
+                     g.Np, tiles_m, tiles_n);
+  return check_launch("packed_fp8_kblock_kernel");
 }
 
 template <int BM, int BN>
@@ -805,7 +791,13 @@ size_t gemm_lowp_workspace(int M, int N, int K, rise_mode mode, const rise_tile&
   return (size_t)round_up((int64_t)prep_bytes(Mp, Kp, mode), 256) + prep_bytes(Np, Kp, mode);
 }
 
+int packed_kblock(rise_mode mode, const rise_tile& t) {
+  return mode == RISE_MODE_FP8 && t.bm == 256 ? kFp8KBlock : 0;
+}
+
 rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStream_t s) {
+  if (g.kblock != packed_kblock(g.mode, t))
+    return fail(RISE_ERR_UNSUPPORTED, "packed gemm: operand layout does not match the tile");
   switch (g.mode) {
     case RISE_MODE_BF16:
       if (t.bm == 256 && t.bk == 32) return launch_bf16_async<256, 256, 32, 4, RISE_MODE_BF16>(g, s);
@@ -819,7 +811,7 @@ rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStrea
       if (t.bm == 256) return launch_bf16<256, 256, 16, RISE_MODE_BF16X6>(g, s);
       return launch_bf16<128, 128, 16, RISE_MODE_BF16X6>(g, s);
     case RISE_MODE_FP8:
-      if (t.bm == 256) return launch_fp8_async<256, 256>(g, s);
+      if (t.bm == 256) return launch_fp8_kblock(g, s);
       return launch_fp8<128, 128>(g, s);
     default:
       return fail(RISE_ERR_UNSUPPORTED, "packed gemm: mode");
@@ -831,15 +823,16 @@ rise_status launch_gemm_lowp(const GemmLowpArgs& a, const rise_tile& t, void* ws
   uint8_t* wsA = (uint8_t*)ws;
   uint8_t* wsB = wsA + round_up((int64_t)prep_bytes(Mp, Kp, a.mode), 256);
   // A: M vectors of length K; B: N vectors of length K (columns of B)
+  const int kb = packed_kblock(a.mode, t);
   PrepArgs pa{wsA, Mp, Kp, a.A, a.M, a.K, a.ta ? 1 : a.lda, a.ta ? a.lda : 1, a.mode,
-              a.tA == RISE_BF16};
+              a.tA == RISE_BF16, kb};
   PrepArgs pb{wsB, Np, Kp, a.B, a.N, a.K, a.tb ? a.ldb : 1, a.tb ? 1 : a.ldb, a.mode,
-              a.tB == RISE_BF16};
+              a.tB == RISE_BF16, kb};
   rise_status st = launch_prep(pa, s);
   if (st != RISE_OK) return st;
   st = launch_prep(pb, s);
   if (st != RISE_OK) return st;
-  PackedGemm g{a.C, a.ldc, wsA, wsB, a.M, a.N, (int)Kp, (int)Mp, (int)Np, a.mode};
+  PackedGemm g{a.C, a.ldc, wsA, wsB, a.M, a.N, (int)Kp, (int)Mp, (int)Np, a.mode, kb};
   return launch_packed_gemm(g, t, s);
 }
 

@@ -73,6 +73,19 @@ __device__ __forceinline__ int e4m3_block_exp(float amax) {
   return e > 127 ? 127 : e;
 }
 
+// element k of row r in a part of rows_out x k_out (kb = 0) or K-blocked by kb
+__device__ __forceinline__ int64_t at(int64_t r, int64_t k, int64_t rows_out, int64_t k_out,
+                                      int kb) {
+  return kb ? ((k / kb) * rows_out + r) * kb + k % kb : r * k_out + k;
+}
+// scale byte of 32-element block b of row r (FP8), the same layouts
+__device__ __forceinline__ int64_t scale_at(int64_t r, int64_t b, int64_t rows_out,
+                                            int64_t k_out, int kb) {
+  if (!kb) return r * (k_out / 32) + b;
+  const int g = kb / 32;
+  return ((b / g) * rows_out + r) * g + b % g;
+}
+
 template <typename SRC>
 __device__ __forceinline__ float load_src(const SRC* p);
 template <>
@@ -87,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(void* __restrict__ out, 
                                                         int64_t k_out,
                                                         const SRC* __restrict__ src,
                                                         int64_t rows, int64_t K, int64_t ld_r,
-                                                        int64_t ld_k, int vec_out) {
+                                                        int64_t ld_k, int vec_out, int kb) {
   __shared__ float tile[TR][TK + 1];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * TR;
@@ -166,7 +179,8 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(void* __restrict__ out, 
     uint8_t q[16];
 #pragma unroll
     for (int e = 0; e < 16; e++) q[e] = e4m3_rne(x[e] * s);
-    uint8_t* o = reinterpret_cast<uint8_t*>(out) + gr * k_out + gk;
+    // 16 codes of one row: inside one K block (gk % 16 == 0, kb a multiple of 32)
+    uint8_t* o = reinterpret_cast<uint8_t*>(out) + at(gr, gk, rows_out, k_out, kb);
     if (full && vec_out) {
       i32x4 v;
 #pragma unroll
@@ -180,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(void* __restrict__ out, 
     }
     if ((kc & 31) == 0 && gk < k_out) {
       uint8_t* sp = reinterpret_cast<uint8_t*>(out) + rows_out * k_out;
-      sp[gr * (k_out / 32) + gk / 32] = (uint8_t)(127 - ex);
+      sp[scale_at(gr, gk / 32, rows_out, k_out, kb)] = (uint8_t)(127 - ex);
     }
     return;
   }
@@ -195,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(void* __restrict__ out, 
       h[e] = bf16_rne(x[e]);
       x[e] = x[e] - bf16_to_f32(h[e]);  // exact residual
     }
-    uint16_t* o = reinterpret_cast<uint16_t*>(out) + p * plane + gr * k_out + gk;
+    uint16_t* o = reinterpret_cast<uint16_t*>(out) + p * plane + at(gr, gk, rows_out, k_out, kb);
     if (full && vec_out) {
       i32x4 v0, v1;
 #pragma unroll
@@ -220,7 +234,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(void* __restrict__ out, 
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void prep_stream_kernel(
     void* __restrict__ out, int64_t rows_out, int64_t k_out, const float* __restrict__ src,
-    int64_t rows, int64_t K, int64_t ld_r, int vec_out) {
+    int64_t rows, int64_t K, int64_t ld_r, int vec_out, int kb) {
   const int64_t chunks = (k_out + 7) / 8;
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (t >= rows_out * chunks) return;
@@ -245,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void prep_stream_kernel(
       h[e] = bf16_rne(x[e]);
       x[e] = x[e] - bf16_to_f32(h[e]);  // exact residual
     }
-    uint16_t* o = reinterpret_cast<uint16_t*>(out) + p * plane + gr * k_out + gk;
+    uint16_t* o = reinterpret_cast<uint16_t*>(out) + p * plane + at(gr, gk, rows_out, k_out, kb);
     if (vec_out && gk + 8 <= k_out) {
       i32x4 v;
 #pragma unroll
@@ -265,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void prep_stream_kernel(
 // lane its scale byte.
 __global__ __launch_bounds__(kThreads) void prep_stream_fp8_kernel(
     uint8_t* __restrict__ out, int64_t rows_out, int64_t k_out, const float* __restrict__ src,
-    int64_t rows, int64_t K, int64_t ld_r) {
+    int64_t rows, int64_t K, int64_t ld_r, int kb) {
   const int64_t chunks = k_out / 8;  // a multiple of 4
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (t >= rows_out * chunks) return;  // whole 4-lane blocks leave together
@@ -293,8 +307,8 @@ __global__ __launch_bounds__(kThreads) void prep_stream_fp8_kernel(
     w0 |= (uint32_t)e4m3_rne(x[e] * sc) << (8 * e);
     w1 |= (uint32_t)e4m3_rne(x[4 + e] * sc) << (8 * e);
   }
-  *reinterpret_cast<uint2*>(out + gr * k_out + gk) = uint2{w0, w1};
-  if ((gk & 31) == 0) out[rows_out * k_out + gr * (k_out / 32) + gk / 32] = (uint8_t)(127 - ex);
+  *reinterpret_cast<uint2*>(out + at(gr, gk, rows_out, k_out, kb)) = uint2{w0, w1};
+  if ((gk & 31) == 0) out[rows_out * k_out + scale_at(gr, gk / 32, rows_out, k_out, kb)] = (uint8_t)(127 - ex);
 }
 
 template <typename SRC, int MODE>
@@ -314,25 +328,25 @@ rise_status launch_mode(const PrepArgs& a, hipStream_t s) {
     const int64_t threads = a.rows_out * ((a.k_out + 7) / 8);
     hipLaunchKernelGGL((prep_stream_kernel<MODE>), dim3((unsigned)((threads + kThreads - 1) / kThreads)),
                        block, 0, s, a.out, a.rows_out, a.k_out, reinterpret_cast<const float*>(a.src),
-                       a.rows, a.K, a.ld_r, vec_out);
+                       a.rows, a.K, a.ld_r, vec_out, a.kblock);
     return check_launch("prep_stream_kernel");
   }
   if (layout == 1 && MODE == RISE_MODE_FP8 && vec_out && a.k_out % 32 == 0) {
     const int64_t threads = a.rows_out * (a.k_out / 8);
     hipLaunchKernelGGL(prep_stream_fp8_kernel, dim3((unsigned)((threads + kThreads - 1) / kThreads)),
                        block, 0, s, reinterpret_cast<uint8_t*>(a.out), a.rows_out, a.k_out,
-                       reinterpret_cast<const float*>(a.src), a.rows, a.K, a.ld_r);
+                       reinterpret_cast<const float*>(a.src), a.rows, a.K, a.ld_r, a.kblock);
     return check_launch("prep_stream_fp8_kernel");
   }
   if (layout == 1)
     hipLaunchKernelGGL((prep_kernel<SRC, MODE, 1>), grid, block, 0, s, a.out, a.rows_out, a.k_out,
-                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out);
+                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out, a.kblock);
   else if (layout == 2)
     hipLaunchKernelGGL((prep_kernel<SRC, MODE, 2>), grid, block, 0, s, a.out, a.rows_out, a.k_out,
-                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out);
+                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out, a.kblock);
   else
     hipLaunchKernelGGL((prep_kernel<SRC, MODE, 0>), grid, block, 0, s, a.out, a.rows_out, a.k_out,
-                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out);
+                       src, a.rows, a.K, a.ld_r, a.ld_k, vec_out, a.kblock);
   return check_launch("prep_kernel");
 }
 
@@ -354,6 +368,8 @@ size_t prep_bytes(int64_t rows_out, int64_t k_out, rise_mode mode) {
 }
 
 rise_status launch_prep(const PrepArgs& a, hipStream_t s) {
+  if (a.kblock < 0 || a.kblock % 32 || (a.kblock && a.k_out % a.kblock))
+    return fail(RISE_ERR_SHAPE, "prep: K block must be a multiple of 32 dividing k_out");
   if (a.rows_out == 0 || a.k_out == 0) return RISE_OK;
   if (a.src_bf16) {
     if (a.mode != RISE_MODE_BF16) return fail(RISE_ERR_DTYPE, "prep: bf16 source needs mode BF16");
