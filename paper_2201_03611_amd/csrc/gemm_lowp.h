@@ -15,9 +15,10 @@ struct PrepArgs {
   rise_mode mode;
   bool src_bf16 = false;
   // 0: each part is rows_out x k_out, K contiguous.  kblock > 0 (a multiple of
-  // 32 dividing k_out): K-blocked, K block b of row r holds kblock consecutive
-  // elements at (b * rows_out + r) * kblock, so one block of consecutive rows
-  // is contiguous; FP8 scale bytes likewise in groups of kblock / 32.
+  // 16, of 32 for FP8, dividing k_out): K-blocked, K block b of row r holds
+  // kblock consecutive elements at (b * rows_out + r) * kblock, so one block of
+  // consecutive rows is contiguous; FP8 scale bytes likewise in groups of
+  // kblock / 32.
   int kblock = 0;
 };
 int prep_parts(rise_mode mode);

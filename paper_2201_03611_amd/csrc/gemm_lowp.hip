@@ -360,19 +360,10 @@ __global__ __launch_bounds__(kThreads, 1) void packed_fp8_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// BF16 / split-BF16 kernel with asynchronous slab copies: the same tiling and
-// contraction as packed_bf16_kernel, but each slab goes from global memory
-// straight into LDS (gfx950 global_load_lds_dwordx4: lane i's 16 bytes land
-// at base + 16 i) through a ring of STAGES buffers.  The copy of slab kt +
-// STAGES - 1 is issued right after the barrier that opens slab kt, so each
-// copy has STAGES - 1 slabs of matrix-core time to arrive, and no registers
-// hold data in transit.  Copy completion is tracked only by vmcnt, so the
-// waits are explicit: before the barrier of slab kt a wave waits until at
-// most the copies of the STAGES - 2 newer slabs are outstanding, and the
-// barrier then publishes every wave's part of slab kt.  The barrier is a
-// bare s_barrier (a workgroup fence would wait for all copies in flight).
-// The swizzle is applied on the global side: lane i of a copy fetches the
-// logical chunk that belongs in LDS slot base + i.
+// Asynchronous slab copies (gfx950 global_load_lds: lane i's bytes land at the
+// wave-uniform LDS base + size * i, no registers hold data in transit).  Copy
+// completion is tracked only by vmcnt, so waits are explicit, and barriers are
+// bare s_barrier (a workgroup fence would wait for every copy in flight).
 // (the instruction text exists only in the device pass)
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
@@ -404,186 +395,69 @@ __device__ __forceinline__ void copy4_to_lds(const void* src, void* lds_base) {
 #endif
 }
 
-template <int BM, int BN, int BK, int STAGES, int MODE, bool XPF>
-__global__ __launch_bounds__(kThreads, 1) void packed_bf16_async_kernel(
-    float* __restrict__ C, int64_t ldc, const uint16_t* __restrict__ Ap,
-    const uint16_t* __restrict__ Bp, int M, int N, int Kp, int Mp, int Np, int tiles_m,
-    int tiles_n) {
-  using P = Parts<MODE>;
-  constexpr int NP = P::n;
-  constexpr int CH = BK / 8;              // 16-byte chunks per slab row
-  constexpr int SLOTS = (BM + BN) * CH;   // chunks per part per stage: A rows, then B rows
-  constexpr int NCP = SLOTS / kThreads;   // copies per thread per part per slab
-  constexpr int WM = BM / 2, WN = BN / 2;
-  constexpr int TM = WM / 32, TN = WN / 32;
-  constexpr int KS = BK / 16;
-  static_assert(SLOTS % kThreads == 0 && STAGES >= 3, "slab shape");
-  static_assert(BM % 16 == 0, "the B rows start on a whole swizzle period");
-  constexpr int INFLIGHT = (STAGES - 2) * NP * NCP;  // copies allowed outstanding at a barrier
-
-  __shared__ i32x4 lds[STAGES][NP][SLOTS];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
-  int tm, tn;
-  grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, 4, tm, tn);
-  const int m0 = tm * BM, n0 = tn * BN;
-  const int64_t planeA = (int64_t)Mp * Kp, planeB = (int64_t)Np * Kp;
-
-  // copy q of this lane fills slot (wave * NCP + q) * 64 + lane of every part
-  const uint16_t* src[NCP];
-  int64_t plane[NCP];
-#pragma unroll
-  for (int q = 0; q < NCP; q++) {
-    const int slot = (wave * NCP + q) * 64 + lane;
-    const int r = slot / CH, pc = slot % CH;
-    const int c = pc ^ ((r / (16 / CH)) % CH);  // inverse of swz<CH> (an involution per row)
-    if (r < BM) {
-      src[q] = Ap + (int64_t)(m0 + r) * Kp + c * 8;
-      plane[q] = planeA;
-    } else {
-      src[q] = Bp + (int64_t)(n0 + r - BM) * Kp + c * 8;
-      plane[q] = planeB;
-    }
-  }
-  const int nk = Kp / BK;
-  auto issue = [&](int kt, int buf) {  // slab min(kt, nk - 1) -> ring buffer buf
-    const int k0 = (kt < nk ? kt : nk - 1) * BK;
-#pragma unroll
-    for (int p = 0; p < NP; p++)
-#pragma unroll
-      for (int q = 0; q < NCP; q++)
-        copy16_to_lds(src[q] + p * plane[q] + k0, &lds[buf][p][(wave * NCP + q) * 64]);
-  };
-
-  f32x16 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; i++)
-#pragma unroll
-    for (int j = 0; j < TN; j++)
-#pragma unroll
-      for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
-
-  const int il = lane & 31, kh = lane >> 5;
-  bf16x8 fa[2][NP][TM], fb[2][NP][TN];
-  auto read_frags = [&](int buf, int ks, int slot) {
-    const int c = 2 * ks + kh;
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-#pragma unroll
-      for (int i = 0; i < TM; i++)
-        fa[slot][p][i] = __builtin_bit_cast(bf16x8, lds[buf][p][swz<CH>(wm0 + 32 * i + il, c)]);
-#pragma unroll
-      for (int j = 0; j < TN; j++)
-        fb[slot][p][j] = __builtin_bit_cast(bf16x8, lds[buf][p][swz<CH>(BM + wn0 + 32 * j + il, c)]);
-    }
-  };
-  auto mfmas = [&](int slot) {
-#pragma unroll
-    for (int q = P::nprod - 1; q >= 0; q--)  // small products first
-#pragma unroll
-      for (int i = 0; i < TM; i++)
-#pragma unroll
-        for (int j = 0; j < TN; j++)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[slot][P::pa(q)][i],
-                                                              fb[slot][P::pb(q)][j], acc[i][j], 0,
-                                                              0, 0);
-  };
-  constexpr int NMF = P::nprod * TM * TN;
-  constexpr int NRD = NP * (TM + TN);
-
-  // XPF: the barrier that opens slab kt also publishes slab kt + 1, so the
-  // first fragments of slab kt + 1 are read under the last MFMAs of slab kt
-  // (no LDS-latency bubble after the barrier), at the price of one slab less
-  // lead time for the copies.
-  constexpr int WAIT = XPF ? (STAGES - 3) * NP * NCP : INFLIGHT;
-  static_assert(!XPF || STAGES >= 4, "cross-slab prefetch needs four buffers");
-  static_assert(!XPF || KS % 2 == 0, "fragment slots alternate per k-step: even k-steps per slab");
-  if (nk > 0) {
-#pragma unroll
-    for (int st = 0; st < STAGES - 1; st++) issue(st, st);
-    if (XPF) {
-      wait_vmcnt<INFLIGHT>();
-      raw_barrier();
-      read_frags(0, 0, 0);
-    }
-  }
-  for (int kt = 0; kt < nk; kt++) {
-    const int buf = kt % STAGES;
-    wait_vmcnt<WAIT>();  // this wave's copies of slab kt (XPF: kt + 1) have landed
-    wait_lgkmcnt0();     // and its reads of the previous slab are done
-    raw_barrier();       // every wave's copies are visible
-    issue(kt + STAGES - 1, (kt + STAGES - 1) % STAGES);  // refills the buffer of slab kt - 1
-    if (!XPF) read_frags(buf, 0, 0);
-#pragma unroll
-    for (int ks = 0; ks < KS; ks++) {
-      const int slot = ks & 1;
-      if (ks + 1 < KS)
-        read_frags(buf, ks + 1, slot ^ 1);
-      else if (XPF)
-        read_frags((kt + 1) % STAGES, 0, slot ^ 1);  // slab kt + 1 (a clamped copy at the end)
-      mfmas(slot);
-    }
-    // instruction order of one slab: copies, then (without XPF) the first
-    // fragments, then every later fragment read paired with an MFMA
-    __builtin_amdgcn_sched_group_barrier(0x020, NP * NCP, 0);
-    if (!XPF) __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
-    constexpr int LATER = XPF ? KS * NRD : (KS - 1) * NRD;
-#pragma unroll
-    for (int t = 0; t < LATER; t++) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, KS * NMF - LATER, 0);
-  }
-  wait_vmcnt<0>();  // the clamped tail copies land before the workgroup ends
-
-  store_tile<TM, TN>(C, ldc, M, N, m0 + wm0, n0 + wn0, lane, acc);
-}
-
 // ---------------------------------------------------------------------------
-// FP8 kernel for 256 x 256 tiles over K-blocked operands (64 codes per block:
-// the 64-byte K slices of consecutive rows are contiguous, and the two scale
-// bytes of a row's slice sit together).  The register staging of
-// packed_fp8_kernel does not fit beside the 256 accumulator registers of a
-// 256 x 256 tile, so each slab (the 64-k slice of the tile's 512 rows, 32 KB,
-// plus 1 KB of scales) goes from global memory straight into LDS with
-// global_load_lds: one copy instruction moves 16 whole rows of 64 bytes, i.e.
-// whole 128-byte lines, which a row-major 64-byte slab would fetch as halves.
-// Slabs flow through a ring of four LDS buffers:
+// 256 x 256 tiles over K-blocked operands, every format.  A K-blocked part
+// holds the K block b of row r (KBB bytes: 64 FP8 codes, 32 bf16 values, or 16
+// for the split formats) at (b * rows + r) * KBB, so the blocks of consecutive
+// rows are contiguous (an FP8 row's two scale bytes of a block sit together in
+// the scale plane).  The register staging of the row-major kernels does not
+// fit beside the 256 accumulator registers of a 256 x 256 tile, so each slab
+// (one K block of the tile's 512 rows in every part, 32 KB, or 48 KB for
+// bf16x6, plus 1 KB of FP8 scales) goes from global memory straight into LDS
+// with global_load_lds: a copy instruction moves 1 KB of consecutive rows,
+// i.e. whole 128-byte lines, which a row-major slab this thin would fetch in
+// pieces.  Slabs flow through a ring of STAGES LDS buffers:
 //   wait for this wave's copies of slab kt+1 and its fragment reads of slab kt;
 //   barrier (slab kt+1 visible; every wave holds slab kt in registers);
-//   copy slab kt+4 into the buffer of slab kt, read slab kt+1's fragments and
-//   run slab kt's 16 MFMAs, the copies and reads interleaved between MFMAs,
-// so a copy has three slabs of MFMA time to land and fragment reads never
+//   copy slab kt+STAGES into the buffer of slab kt, read slab kt+1's
+//   fragments and run slab kt's MFMAs, the copies and reads interleaved
+//   between MFMAs,
+// so a copy has STAGES - 1 slabs of MFMA time to land and fragment reads never
 // stall the matrix core.  Codes and scales share one LDS array: the compiler
 // then adds no wait for the copies in flight in front of the fragment reads.
+// Per accumulator the products run in the same order as in the row-major
+// kernels (k-steps in order; split products small first), so results match
+// them bit for bit.
 __device__ __forceinline__ void wait_lgkmcnt0_visible() {
   // s_waitcnt lgkmcnt(0) (vmcnt and expcnt fields at their maxima) as an
   // instruction the compiler's own wait insertion accounts for
   __builtin_amdgcn_s_waitcnt(0xC07F);
 }
 
-constexpr int kFp8KBlock = 64;
+template <int MODE>
+struct KBlock {
+  static constexpr bool fp8 = MODE == RISE_MODE_FP8;
+  static constexpr int parts = fp8 ? 1 : Parts<MODE>::n;
+  static constexpr int nprod = fp8 ? 1 : Parts<MODE>::nprod;
+  static constexpr int bytes = parts == 1 ? 64 : 32;  // KBB: bytes of a K block per part
+  static constexpr int elems = bytes / (fp8 ? 1 : 2);  // K per slab
+  static constexpr int ksteps = fp8 ? 1 : elems / 16;  // MFMA k-steps per slab
+  static constexpr int stages = parts == 3 ? 3 : 4;
+};
 
-__global__ __launch_bounds__(kThreads, 1) void packed_fp8_kblock_kernel(
-    float* __restrict__ C, int64_t ldc, const uint8_t* __restrict__ Ap,
-    const uint8_t* __restrict__ Bp, int M, int N, int Kp, int Mp, int Np, int tiles_m,
+template <int MODE>
+__global__ __launch_bounds__(kThreads, 1) void packed_kblock_kernel(
+    float* __restrict__ C, int64_t ldc, const void* __restrict__ Apv,
+    const void* __restrict__ Bpv, int M, int N, int Kp, int Mp, int Np, int tiles_m,
     int tiles_n) {
-  constexpr int BM = 256, BN = 256, KB = kFp8KBlock, CH = KB / 16;
+  using KC = KBlock<MODE>;
+  constexpr bool FP8 = KC::fp8;
+  constexpr int NP = KC::parts, KBB = KC::bytes, KS = KC::ksteps, STAGES = KC::stages;
+  constexpr int ES = FP8 ? 1 : 2;             // bytes per element
+  constexpr int BM = 256, BN = 256, CH = KBB / 16;
   constexpr int ROWS = BM + BN;
-  constexpr int STAGES = 4;
-  constexpr int CODE_SLOTS = ROWS * CH;       // 16-byte chunks of one buffer
-  constexpr int NCP = CODE_SLOTS / kThreads;  // 8 code copies per thread per slab
-  constexpr int NPS = NCP + 1;                // copies per wave per slab, scales included
-  constexpr int SCW = ROWS * (KB / 32) / 4;   // scale words of one slab
+  constexpr int CODE_SLOTS = ROWS * CH;       // 16-byte chunks of one part of a buffer
+  constexpr int NCP = CODE_SLOTS / kThreads;  // copies per thread per part per slab
+  constexpr int NPS = NP * NCP + (FP8 ? 1 : 0);  // copies per wave per slab
+  constexpr int SCW = FP8 ? ROWS * 2 / 4 : 0; // scale words of one slab
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
-  static_assert(SCW == kThreads, "one scale word per thread");
+  static_assert(!FP8 || SCW == kThreads, "one scale word per thread");
   static_assert((STAGES - 1) * NPS < 64, "vmcnt field");
+  static_assert(NCP % 2 == 0, "a wave's copies stay within A or within B rows");
 
-  __shared__ i32x4 lds[STAGES * CODE_SLOTS + STAGES * SCW / 4];
+  __shared__ i32x4 lds[STAGES * NP * CODE_SLOTS + STAGES * SCW / 4];
   i32x4* const codes = lds;
-  uint32_t* const scale_words = reinterpret_cast<uint32_t*>(lds + STAGES * CODE_SLOTS);
+  uint32_t* const scale_words = reinterpret_cast<uint32_t*>(lds + STAGES * NP * CODE_SLOTS);
   const uint8_t* const scale_bytes = reinterpret_cast<const uint8_t*>(scale_words);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -593,34 +467,40 @@ __global__ __launch_bounds__(kThreads, 1) void packed_fp8_kblock_kernel(
   const int m0 = tm * BM, n0 = tn * BN;
 
   // waves 0, 1 copy the A rows of a slab, waves 2, 3 the B rows; slot
-  // (wave * NCP + q) * 64 + lane of a buffer holds row slot / CH, physical
-  // chunk slot % CH, i.e. the logical chunk given by the swizzle's inverse
+  // (wave * NCP + q) * 64 + lane of a part's buffer holds row slot / CH,
+  // physical chunk slot % CH, i.e. the logical chunk given by the swizzle's
+  // inverse
   const bool isB = wave >= 2;
   const int64_t prows = isB ? Np : Mp;
-  const uint8_t* const plane = isB ? Bp : Ap;
-  const uint8_t* const splane = plane + prows * Kp;
+  const uint8_t* const plane = reinterpret_cast<const uint8_t*>(isB ? Bpv : Apv);
+  const int64_t part_bytes = prows * Kp * ES;
+  const uint8_t* const splane = plane + part_bytes;  // FP8 scales follow the codes
   const int64_t row0 = isB ? n0 : m0;
-  int coff[NCP];
+  int coff[NCP];  // bytes
 #pragma unroll
   for (int q = 0; q < NCP; q++) {
     const int slot = (wave * NCP + q) * 64 + lane;
     const int r = slot / CH, pc = slot % CH;
     const int c = pc ^ ((r / (16 / CH)) % CH);
-    coff[q] = (isB ? r - BM : r) * KB + c * 16;
+    coff[q] = (isB ? r - BM : r) * KBB + c * 16;
   }
-  // scale word tid of a slab: bytes 4 tid .. 4 tid + 3 of the A rows' pairs
-  // (words 0-127) then the B rows' pairs (words 128-255)
+  // FP8 scale word tid of a slab: bytes 4 tid .. 4 tid + 3 of the A rows'
+  // pairs (words 0-127) then the B rows' pairs (words 128-255)
   const int soff = (isB ? tid - kThreads / 2 : tid) * 4;
 
-  const int nk = Kp / KB;
+  const int nk = Kp / KC::elems;
   auto issue = [&](int kt) {  // slab min(kt, nk - 1) -> buffer kt % STAGES
     const int64_t k = kt < nk ? kt : nk - 1;
     const int buf = kt % STAGES;
-    const uint8_t* cb = plane + (k * prows + row0) * KB;
+    const uint8_t* cb = plane + (k * prows + row0) * KBB;
 #pragma unroll
-    for (int q = 0; q < NCP; q++)
-      copy16_to_lds(cb + coff[q], codes + buf * CODE_SLOTS + (wave * NCP + q) * 64);
-    copy4_to_lds(splane + (k * prows + row0) * (KB / 32) + soff, scale_words + buf * SCW + wave * 64);
+    for (int p = 0; p < NP; p++)
+#pragma unroll
+      for (int q = 0; q < NCP; q++)
+        copy16_to_lds(cb + p * part_bytes + coff[q],
+                      codes + (buf * NP + p) * CODE_SLOTS + (wave * NCP + q) * 64);
+    if constexpr (FP8)
+      copy4_to_lds(splane + (k * prows + row0) * 2 + soff, scale_words + buf * SCW + wave * 64);
   };
 
   f32x16 acc[TM][TN];
@@ -631,27 +511,43 @@ __global__ __launch_bounds__(kThreads, 1) void packed_fp8_kblock_kernel(
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
 
-  // fragments of one slab (the same operand and scale layout as
-  // packed_fp8_kernel's k-step 0): two register sets, alternating by slab
+  // fragments of one slab, two register sets alternating by slab.  FP8: the
+  // operand and scale layout of packed_fp8_kernel's k-step 0; bf16: k-step s
+  // of the slab takes chunk 2 s + kh (lanes 0-31 k 0-7, lanes 32-63 k 8-15)
   const int il = lane & 31, kh = lane >> 5;
-  i32x8 fa[2][TM], fb[2][TN];
+  i32x8 fa8[2][TM], fb8[2][TN];
   int xa[2][TM], xb[2][TN];
+  bf16x8 fa16[2][NP][KS][TM], fb16[2][NP][KS][TN];
   auto reads = [&](int buf, int set) {
-    const i32x4* cb = codes + buf * CODE_SLOTS;
-    const uint8_t* sb = scale_bytes + buf * SCW * 4;
 #pragma unroll
-    for (int i = 0; i < TM; i++) {
-      const int r = wm0 + 32 * i + il;
-      const i32x4 lo = cb[swz<CH>(r, kh)], hi = cb[swz<CH>(r, 2 + kh)];
-      fa[set][i] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      xa[set][i] = sb[r * 2 + kh];
-    }
+    for (int p = 0; p < NP; p++) {
+      const i32x4* cb = codes + (buf * NP + p) * CODE_SLOTS;
 #pragma unroll
-    for (int j = 0; j < TN; j++) {
-      const int r = BM + wn0 + 32 * j + il;
-      const i32x4 lo = cb[swz<CH>(r, kh)], hi = cb[swz<CH>(r, 2 + kh)];
-      fb[set][j] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      xb[set][j] = sb[r * 2 + kh];
+      for (int i = 0; i < TM; i++) {
+        const int r = wm0 + 32 * i + il;
+        if constexpr (FP8) {
+          const i32x4 lo = cb[swz<CH>(r, kh)], hi = cb[swz<CH>(r, 2 + kh)];
+          fa8[set][i] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+          xa[set][i] = scale_bytes[buf * SCW * 4 + r * 2 + kh];
+        } else {
+#pragma unroll
+          for (int ks = 0; ks < KS; ks++)
+            fa16[set][p][ks][i] = __builtin_bit_cast(bf16x8, cb[swz<CH>(r, 2 * ks + kh)]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < TN; j++) {
+        const int r = BM + wn0 + 32 * j + il;
+        if constexpr (FP8) {
+          const i32x4 lo = cb[swz<CH>(r, kh)], hi = cb[swz<CH>(r, 2 + kh)];
+          fb8[set][j] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+          xb[set][j] = scale_bytes[buf * SCW * 4 + r * 2 + kh];
+        } else {
+#pragma unroll
+          for (int ks = 0; ks < KS; ks++)
+            fb16[set][p][ks][j] = __builtin_bit_cast(bf16x8, cb[swz<CH>(r, 2 * ks + kh)]);
+        }
+      }
     }
   };
   auto step = [&](int kt, auto set_tag) {
@@ -663,20 +559,35 @@ __global__ __launch_bounds__(kThreads, 1) void packed_fp8_kblock_kernel(
     __builtin_amdgcn_sched_barrier(0);
     issue(kt + STAGES);                // refills the buffer of slab kt
     reads((kt + 1) % STAGES, set ^ 1);  // slab kt+1 (past the end: a clamped copy, unused)
+    if constexpr (FP8) {
 #pragma unroll
-    for (int i = 0; i < TM; i++)
+      for (int i = 0; i < TM; i++)
 #pragma unroll
-      for (int j = 0; j < TN; j++)
-        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[set][i], fb[set][j],
-                                                                   acc[i][j], 0, 0, 0,
-                                                                   xa[set][i], 0, xb[set][j]);
+        for (int j = 0; j < TN; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              fa8[set][i], fb8[set][j], acc[i][j], 0, 0, 0, xa[set][i], 0, xb[set][j]);
+    } else {
+      using P = Parts<MODE>;
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++)
+#pragma unroll
+        for (int q = P::nprod - 1; q >= 0; q--)  // small products first
+#pragma unroll
+          for (int i = 0; i < TM; i++)
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  fa16[set][P::pa(q)][ks][i], fb16[set][P::pb(q)][ks][j], acc[i][j], 0, 0, 0);
+    }
     // one MFMA, then a copy while copies remain, then the fragment reads
-    constexpr int NRD = 3 * (TM + TN);  // two 16-byte reads and a scale byte per fragment
+    constexpr int NMF = KS * KC::nprod * TM * TN;
+    constexpr int NRD = FP8 ? 3 * (TM + TN) : NP * KS * (TM + TN);
+    constexpr int RPM = (NRD + NMF - 1) / NMF;
 #pragma unroll
-    for (int t = 0; t < TM * TN; t++) {
+    for (int t = 0; t < NMF; t++) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       if (t < NPS) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, (NRD + TM * TN - 1) / (TM * TN), 0);
+      if (t * RPM < NRD) __builtin_amdgcn_sched_group_barrier(0x100, RPM, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -728,25 +639,12 @@ rise_status launch_bf16(const PackedGemm& g, hipStream_t s) {
   return check_launch("packed_bf16_kernel");
 }
 
-constexpr bool kAsyncXpf = false;
-
-template <int BM, int BN, int BK, int STAGES, int MODE>
-rise_status launch_bf16_async(const PackedGemm& g, hipStream_t s) {
-  int tiles_m = g.Mp / BM, tiles_n = g.Np / BN;
-  hipLaunchKernelGGL(
-      (packed_bf16_async_kernel<BM, BN, BK, STAGES, MODE, (kAsyncXpf && (BK / 16) % 2 == 0)>),
-                     dim3(tiles_m * tiles_n), dim3(kThreads), 0, s, g.C, g.ldc,
-                     (const uint16_t*)g.Ap, (const uint16_t*)g.Bp, g.M, g.N, g.Kp, g.Mp, g.Np,
-                     tiles_m, tiles_n);
-  return check_launch("packed_bf16_async_kernel");
-}
-
-rise_status launch_fp8_kblock(const PackedGemm& g, hipStream_t s) {
+template <int MODE>
+rise_status launch_kblock(const PackedGemm& g, hipStream_t s) {
   int tiles_m = g.Mp / 256, tiles_n = g.Np / 256;
-  hipLaunchKernelGGL(packed_fp8_kblock_kernel, dim3(tiles_m * tiles_n), dim3(kThreads), 0, s,
-                     g.C, g.ldc, (const uint8_t*)g.Ap, (const uint8_t*)g.Bp, g.M, g.N, g.Kp, g.Mp,
-                     g.Np, tiles_m, tiles_n);
-  return check_launch("packed_fp8_kblock_kernel");
+  hipLaunchKernelGGL(packed_kblock_kernel<MODE>, dim3(tiles_m * tiles_n), dim3(kThreads), 0, s,
+                     g.C, g.ldc, g.Ap, g.Bp, g.M, g.N, g.Kp, g.Mp, g.Np, tiles_m, tiles_n);
+  return check_launch("packed_kblock_kernel");
 }
 
 template <int BM, int BN>
@@ -777,13 +675,20 @@ bool gemm_lowp_tile_supported(rise_mode mode, const rise_tile& t) {
 }
 
 rise_tile gemm_lowp_default_tile(rise_mode mode, int M, int N, int K) {
-  // 256 x 256 when it still gives every CU a tile, else 128 x 128 (measured
-  // at 8192^3: bf16 1.14 vs 1.23 ms, bf16x3 3.09 vs 3.22 ms, fp8 with the
-  // asynchronous kernel 0.52-0.61 vs 0.71-0.80 ms)
-  const int bk = mode == RISE_MODE_BF16 ? 64 : mode == RISE_MODE_BF16X3 ? 32
-               : mode == RISE_MODE_BF16X6 ? 16 : 128;
+  // 256 x 256 when it still gives every CU a tile, else 128 x 128; at 256 x
+  // 256 the K-blocked kernel where it is the faster one (measured at 8192^3
+  // with preparation: bf16 1.08-1.24 ms against 1.12-1.32 for the row-major
+  // 256 x 256 x 64 tile, bf16x3 2.71-2.91 against 3.12-3.18 ms for 256 x 256
+  // x 32, bf16x6 5.06 against 6.78 ms for the row-major 256 x 256 x 16 tile,
+  // fp8 0.62 against 0.83 ms for 128 x 128)
   long tiles_big = (long)((M + 255) / 256) * ((N + 255) / 256);
-  return tiles_big >= 256 ? rise_tile{256, 256, bk} : rise_tile{128, 128, bk};
+  const bool big = tiles_big >= 256;
+  switch (mode) {
+    case RISE_MODE_BF16: return big ? rise_tile{256, 256, 32} : rise_tile{128, 128, 64};
+    case RISE_MODE_BF16X3: return big ? rise_tile{256, 256, 16} : rise_tile{128, 128, 32};
+    case RISE_MODE_BF16X6: return big ? rise_tile{256, 256, 16} : rise_tile{128, 128, 16};
+    default: return big ? rise_tile{256, 256, 128} : rise_tile{128, 128, 128};
+  }
 }
 
 size_t gemm_lowp_workspace(int M, int N, int K, rise_mode mode, const rise_tile& t) {
@@ -791,8 +696,15 @@ size_t gemm_lowp_workspace(int M, int N, int K, rise_mode mode, const rise_tile&
   return (size_t)round_up((int64_t)prep_bytes(Mp, Kp, mode), 256) + prep_bytes(Np, Kp, mode);
 }
 
+// K-blocked layout (K per block) of the tiles packed_kblock_kernel runs
 int packed_kblock(rise_mode mode, const rise_tile& t) {
-  return mode == RISE_MODE_FP8 && t.bm == 256 ? kFp8KBlock : 0;
+  if (mode == RISE_MODE_FP8 && t.bm == 256) return KBlock<RISE_MODE_FP8>::elems;
+  if (mode == RISE_MODE_BF16 && t.bm == 256 && t.bk == 32) return KBlock<RISE_MODE_BF16>::elems;
+  if (mode == RISE_MODE_BF16X3 && t.bm == 256 && t.bk == 16)
+    return KBlock<RISE_MODE_BF16X3>::elems;
+  if (mode == RISE_MODE_BF16X6 && t.bm == 256 && t.bk == 16)
+    return KBlock<RISE_MODE_BF16X6>::elems;
+  return 0;
 }
 
 rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStream_t s) {
@@ -800,18 +712,18 @@ rise_status launch_packed_gemm(const PackedGemm& g, const rise_tile& t, hipStrea
     return fail(RISE_ERR_UNSUPPORTED, "packed gemm: operand layout does not match the tile");
   switch (g.mode) {
     case RISE_MODE_BF16:
-      if (t.bm == 256 && t.bk == 32) return launch_bf16_async<256, 256, 32, 4, RISE_MODE_BF16>(g, s);
+      if (t.bm == 256 && t.bk == 32) return launch_kblock<RISE_MODE_BF16>(g, s);
       if (t.bm == 256) return launch_bf16<256, 256, 64, RISE_MODE_BF16>(g, s);
       return launch_bf16<128, 128, 64, RISE_MODE_BF16>(g, s);
     case RISE_MODE_BF16X3:
-      if (t.bm == 256 && t.bk == 16) return launch_bf16_async<256, 256, 16, 4, RISE_MODE_BF16X3>(g, s);
+      if (t.bm == 256 && t.bk == 16) return launch_kblock<RISE_MODE_BF16X3>(g, s);
       if (t.bm == 256) return launch_bf16<256, 256, 32, RISE_MODE_BF16X3>(g, s);
       return launch_bf16<128, 128, 32, RISE_MODE_BF16X3>(g, s);
     case RISE_MODE_BF16X6:
-      if (t.bm == 256) return launch_bf16<256, 256, 16, RISE_MODE_BF16X6>(g, s);
+      if (t.bm == 256) return launch_kblock<RISE_MODE_BF16X6>(g, s);
       return launch_bf16<128, 128, 16, RISE_MODE_BF16X6>(g, s);
     case RISE_MODE_FP8:
-      if (t.bm == 256) return launch_fp8_kblock(g, s);
+      if (t.bm == 256) return launch_kblock<RISE_MODE_FP8>(g, s);
       return launch_fp8<128, 128>(g, s);
     default:
       return fail(RISE_ERR_UNSUPPORTED, "packed gemm: mode");

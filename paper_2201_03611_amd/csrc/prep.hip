@@ -86,6 +86,37 @@ __device__ __forceinline__ int64_t scale_at(int64_t r, int64_t b, int64_t rows_o
   return ((b / g) * rows_out + r) * g + b % g;
 }
 
+// Thread -> (row, first of 8 consecutive K) for the streaming kernels.  By
+// default lanes run along a row (a wave reads 2 KB of one row; its writes are
+// one contiguous run, or 64-byte K blocks rows_out * kb apart).  K blocks
+// narrower than 64 bytes (kb = 16 bf16 values, rows_out a multiple of 8): a
+// wave takes 8 rows x 64 K, 8 lanes per row, and consecutive waves take
+// consecutive row groups, so a block's writes from consecutive rows are
+// adjacent (256-byte runs) instead of 32-byte pieces (8192^2 bf16x3: 115
+// against 207 us; the 64-byte blocks of bf16 and FP8 stream faster along rows,
+// 78-82 against 108-113 us).
+__device__ __forceinline__ bool narrow_blocks(int kb, int elem_bytes) {
+  return kb && kb * elem_bytes < 64;
+}
+__device__ __forceinline__ bool stream_pos(int64_t t, int64_t rows_out, int64_t k_out, int kb,
+                                           int elem_bytes, int64_t& gr, int64_t& gk) {
+  if (!narrow_blocks(kb, elem_bytes)) {
+    const int64_t chunks = (k_out + 7) / 8;
+    gr = t / chunks;
+    gk = (t - gr * chunks) * 8;
+    return gr < rows_out;
+  }
+  const int64_t w = t >> 6, groups = rows_out / 8;
+  const int l = (int)(t & 63);
+  gr = (w % groups) * 8 + l / 8;
+  gk = (w / groups) * 64 + (l % 8) * 8;
+  return gk < k_out;
+}
+inline int64_t stream_threads(int64_t rows_out, int64_t k_out, int kb, int elem_bytes) {
+  return kb && kb * elem_bytes < 64 ? (rows_out / 8) * ((k_out + 63) / 64) * 64
+                                    : rows_out * ((k_out + 7) / 8);
+}
+
 template <typename SRC>
 __device__ __forceinline__ float load_src(const SRC* p);
 template <>
@@ -229,16 +260,14 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(void* __restrict__ out, 
 // Source rows already K-contiguous (ld_k == 1, 16-byte aligned rows): no
 // transpose is needed, so the bf16 modes stream without LDS.  Each thread
 // converts 8 consecutive K of one row (two 16-byte loads, one 16-byte store
-// per part); consecutive lanes take consecutive chunks of a row, so a wave
-// reads 2 KB and writes 1 KB per part contiguously.
+// per part), threads placed by stream_pos.
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void prep_stream_kernel(
     void* __restrict__ out, int64_t rows_out, int64_t k_out, const float* __restrict__ src,
     int64_t rows, int64_t K, int64_t ld_r, int vec_out, int kb) {
-  const int64_t chunks = (k_out + 7) / 8;
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= rows_out * chunks) return;
-  const int64_t gr = t / chunks, gk = (t - gr * chunks) * 8;
+  int64_t gr, gk;
+  if (!stream_pos(t, rows_out, k_out, kb, 2, gr, gk)) return;
   float x[8];
   if (gr < rows && gk + 8 <= K) {
     const f32x4* q = reinterpret_cast<const f32x4*>(src + gr * ld_r + gk);
@@ -280,10 +309,10 @@ __global__ __launch_bounds__(kThreads) void prep_stream_kernel(
 __global__ __launch_bounds__(kThreads) void prep_stream_fp8_kernel(
     uint8_t* __restrict__ out, int64_t rows_out, int64_t k_out, const float* __restrict__ src,
     int64_t rows, int64_t K, int64_t ld_r, int kb) {
-  const int64_t chunks = k_out / 8;  // a multiple of 4
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= rows_out * chunks) return;  // whole 4-lane blocks leave together
-  const int64_t gr = t / chunks, gk = (t - gr * chunks) * 8;
+  int64_t gr, gk;
+  // k_out is a multiple of 32, so whole 4-lane blocks leave together
+  if (!stream_pos(t, rows_out, k_out, kb, 1, gr, gk)) return;
   float x[8];
   if (gr < rows && gk + 8 <= K) {
     const f32x4* q = reinterpret_cast<const f32x4*>(src + gr * ld_r + gk);
@@ -325,14 +354,14 @@ rise_status launch_mode(const PrepArgs& a, hipStream_t s) {
     else if (a.ld_r == 1 && a.ld_k % 4 == 0) layout = 2;
   }
   if (layout == 1 && MODE != RISE_MODE_FP8) {
-    const int64_t threads = a.rows_out * ((a.k_out + 7) / 8);
+    const int64_t threads = stream_threads(a.rows_out, a.k_out, a.kblock, 2);
     hipLaunchKernelGGL((prep_stream_kernel<MODE>), dim3((unsigned)((threads + kThreads - 1) / kThreads)),
                        block, 0, s, a.out, a.rows_out, a.k_out, reinterpret_cast<const float*>(a.src),
                        a.rows, a.K, a.ld_r, vec_out, a.kblock);
     return check_launch("prep_stream_kernel");
   }
   if (layout == 1 && MODE == RISE_MODE_FP8 && vec_out && a.k_out % 32 == 0) {
-    const int64_t threads = a.rows_out * (a.k_out / 8);
+    const int64_t threads = stream_threads(a.rows_out, a.k_out, a.kblock, 1);
     hipLaunchKernelGGL(prep_stream_fp8_kernel, dim3((unsigned)((threads + kThreads - 1) / kThreads)),
                        block, 0, s, reinterpret_cast<uint8_t*>(a.out), a.rows_out, a.k_out,
                        reinterpret_cast<const float*>(a.src), a.rows, a.K, a.ld_r, a.kblock);
@@ -368,8 +397,12 @@ size_t prep_bytes(int64_t rows_out, int64_t k_out, rise_mode mode) {
 }
 
 rise_status launch_prep(const PrepArgs& a, hipStream_t s) {
-  if (a.kblock < 0 || a.kblock % 32 || (a.kblock && a.k_out % a.kblock))
-    return fail(RISE_ERR_SHAPE, "prep: K block must be a multiple of 32 dividing k_out");
+  // whole 16-element runs of a thread stay in one block; FP8 scale bytes pair up
+  const int kb_unit = a.mode == RISE_MODE_FP8 ? 32 : 16;
+  if (a.kblock < 0 || a.kblock % kb_unit || (a.kblock && (a.k_out % a.kblock || a.rows_out % 8)))
+    return fail(RISE_ERR_SHAPE,
+                "prep: K block must be a multiple of 16 (FP8: 32) dividing k_out, rows_out a "
+                "multiple of 8");
   if (a.rows_out == 0 || a.k_out == 0) return RISE_OK;
   if (a.src_bf16) {
     if (a.mode != RISE_MODE_BF16) return fail(RISE_ERR_DTYPE, "prep: bf16 source needs mode BF16");
