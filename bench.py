@@ -663,7 +663,10 @@ def precision_leg(rise, ri, np, torch, dev, stream):
     out["equal_error_bound"] = 1e-5
     out["note"] = ("times include operand preparation; errors over 604 sampled outputs against "
                    "the exact product of the FP32 inputs: componentwise max |c_hat - c| / "
-                   "(|A||B|)_ij (the bar), normwise, and elementwise over |c| >= 1e-3 max|c|")
+                   "(|A||B|)_ij (the bar), normwise, and elementwise over |c| >= 1e-3 max|c|; "
+                   "ms_prep is the row-major preparation of rise_prep_operand, while the "
+                   "256x256 tiles prepare their operands K-blocked inside rise_gemm (same "
+                   "bytes, a different write order)")
     return out
 
 
