@@ -230,6 +230,40 @@ def test_modes_match_mode_oracle(rise, mode, ops):
         assert err <= TOL_F32, tile
 
 
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("ops", [(False, False), (True, True)])
+@pytest.mark.parametrize("pad", [4, 3])
+def test_modes_padded_leading_dimensions_every_tile(rise, mode, ops, pad):
+    # leading dimensions past the rows, NaN in the padding: pad 4 keeps 16-byte
+    # rows (vector preparation), pad 3 forces the scalar one; both write the
+    # row-major and the K-blocked operand layouts, which must agree bit for bit
+    import torch
+
+    M, N, K = 300, 270, 200
+    g = ri.rng(101 + pad + 2 * ops[0])
+    A = ri.integer_matrix(g, M, K, bound=2)
+    B = ri.integer_matrix(g, K, N, bound=2)
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+
+    def padded(X):
+        r, c = X.shape
+        P = np.full((r, c + pad), np.nan, np.float32)
+        P[:, :c] = X
+        return P
+
+    As = padded(np.ascontiguousarray(A.T) if ops[0] else A)
+    Bs = padded(np.ascontiguousarray(B.T) if ops[1] else B)
+    dA, dB = dev(As), dev(Bs)
+    for tile in rise.rise_gemm_tiles(mode):
+        C = torch.full((M, N), float("nan"), device="cuda", dtype=torch.float32)
+        ws = torch.empty(rise.rise_gemm_workspace(M, N, K, mode, tile), device="cuda",
+                         dtype=torch.uint8)
+        print(f"gemm {mode} padded ld pad={pad} ops={ops} tile={tile}", flush=True)
+        rise.rise_gemm(C, dA, dB, M, N, K, lda=As.shape[1], ldb=Bs.shape[1], ldc=N,
+                       opA=int(ops[0]), opB=int(ops[1]), mode=mode, tile=tile, ws=ws)
+        assert np.array_equal(host(C), exact), tile
+
+
 def test_bf16_stored_operands(rise):
     import torch
 
