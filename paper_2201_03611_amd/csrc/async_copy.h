@@ -39,10 +39,28 @@ __device__ __forceinline__ void barrier() {
 #endif
 }
 
-// 16 bytes per lane, global -> LDS at lds_base + 16 * lane (lds_base wave-uniform)
+// 16 bytes per lane, global -> LDS at lds_base + 16 * lane (lds_base wave-uniform).
+// Written as inline asm (the LDS base goes to M0 through the operand
+// constraint): issued through the builtin, the copy counts for the compiler as
+// a memory access that may touch both global memory and LDS, and while one is
+// outstanding it can only wait for LDS reads with lgkmcnt(0), which exposes the
+// latency of the newest fragment read before every MFMA that needs an older
+// one.  Hidden from the compiler, the copies are tracked by the explicit vmcnt
+// waits alone (the compiler's own vmcnt waits stay safe: loads retire in
+// order, so untracked copies only make them wait longer).
 __device__ __forceinline__ void copy16(const void* src, void* lds_base) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
+  const uint32_t base = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)((__attribute__((address_space(3))) char*)lds_base));
+  asm volatile("global_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(base) : "memory");
+#endif
+}
+// 4 bytes per lane, global -> LDS at lds_base + 4 * lane, the same way
+__device__ __forceinline__ void copy4(const void* src, void* lds_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t base = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)((__attribute__((address_space(3))) char*)lds_base));
+  asm volatile("global_load_lds_dword %0, off" ::"v"(src), "{m0}"(base) : "memory");
 #endif
 }
 

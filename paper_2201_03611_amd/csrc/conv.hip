@@ -22,6 +22,7 @@
 
 #include <algorithm>
 
+#include "async_copy.h"
 #include "common.h"
 #include "conv.h"
 
@@ -87,9 +88,7 @@ __device__ __forceinline__ int wslot(int o, int k) {
 // and a barrier without the workgroup fence (a fence would also wait for the
 // copies in flight).  The instruction text exists only in the device pass.
 __device__ __forceinline__ void copy16_to_lds(const void* src, void* lds_base) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
-#endif
+  async::copy16(src, lds_base);
 }
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {

@@ -18,6 +18,7 @@
 //   split compensation                   -> the extra products (hi.lo, lo.hi,
 //                                           ...) accumulate into the same
 //                                           registers: no extra pass over C.
+#include "async_copy.h"
 #include "gemm_lowp.h"
 
 #include <type_traits>
@@ -382,17 +383,13 @@ __device__ __forceinline__ void raw_barrier() {
   asm volatile("s_barrier" ::: "memory");
 #endif
 }
-// 16 bytes per lane, global -> LDS at lds_base + 16 * lane (lds_base wave-uniform)
+// 16 (4) bytes per lane, global -> LDS at lds_base + 16 (4) * lane
+// (lds_base wave-uniform), through the inline-asm copies of async_copy.h
 __device__ __forceinline__ void copy16_to_lds(const void* src, void* lds_base) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
-#endif
+  async::copy16(src, lds_base);
 }
-// 4 bytes per lane, global -> LDS at lds_base + 4 * lane
 __device__ __forceinline__ void copy4_to_lds(const void* src, void* lds_base) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  __builtin_amdgcn_global_load_lds(src, lds_base, 4, 0, 0);
-#endif
+  async::copy4(src, lds_base);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,8 +410,10 @@ __device__ __forceinline__ void copy4_to_lds(const void* src, void* lds_base) {
 //   fragments and run slab kt's MFMAs, the copies and reads interleaved
 //   between MFMAs,
 // so a copy has STAGES - 1 slabs of MFMA time to land and fragment reads never
-// stall the matrix core.  Codes and scales share one LDS array: the compiler
-// then adds no wait for the copies in flight in front of the fragment reads.
+// stall the matrix core.  The copies are the inline-asm ones of async_copy.h,
+// so the compiler adds no wait for them in front of the fragment reads (issued
+// through the builtin into two LDS arrays, codes and scales, they drew a
+// vmcnt(0) before every slab's first read).
 // Per accumulator the products run in the same order as in the row-major
 // kernels (k-steps in order; split products small first), so results match
 // them bit for bit.
