@@ -66,14 +66,6 @@ __global__ void conv_prep_weights(uint16_t* __restrict__ dst, uint16_t* __restri
   }
 }
 
-// 16-byte chunk c of halo pixel p (CH chunks per pixel) -> LDS chunk index.  A
-// 16-lane group of ds_read_b128 is served from one 256-byte line (64 banks): the
-// XOR key changes every 16/CH pixels so 16 consecutive pixels at one logical
-// chunk use 16 distinct slots.
-template <int CH>
-__device__ __forceinline__ int halo_slot(int p, int c) {
-  return p * CH + (c ^ ((p / (16 / CH)) % CH));
-}
 // chunk k of weight row o -> LDS chunk index; rows are padded to KCP chunks (a
 // multiple of 8, KCP = 8 mod 16 for the shapes here) so the XOR stays inside the
 // row, and the key (o / 2) spreads 16 consecutive rows over 16 slots
@@ -125,9 +117,11 @@ __device__ __forceinline__ void raw_barrier() {
 //     tail re-copies the band's last tile into a free buffer) and the same
 //     stores (out-of-image outputs go to a 256-byte dump page), so "the copies
 //     of tile i+1 have landed" is a fixed vmcnt;
-//   * 16-byte chunks are XOR-swizzled by pixel (halo_slot) so the 16 pixels a
-//     lane group reads at one chunk hit distinct bank slots; the copies apply
-//     the swizzle on the global side;
+//   * halo pixels sit at an odd pitch of CH + 1 16-byte chunks (one chunk of
+//     padding per pixel, filled from the zero page), so the 16 pixels a lane
+//     group reads at one chunk hit 16 distinct bank slots, and every fragment
+//     read of a row is one base register plus an immediate offset (a swizzle
+//     would cost address arithmetic per read);
 //   * the D layout gives each lane 4 consecutive output channels of a pixel
 //     per register group: rounded to bf16 and stored as 8 bytes.
 template <int CI, int CO>
@@ -139,7 +133,8 @@ struct FwdCfg {
   static constexpr int RPW = WPR == 4 ? 2 : 1;      // rows each wave computes, one after the other
   static constexpr int TYF = 4 / WPR * RPW;         // tile rows
   static constexpr int KS = TAPS * CI / 16;         // k-steps of 16
-  static constexpr int SLOTS = (TYF + 2) * HC * CH; // halo chunks
+  static constexpr int PITCH = CH + 1;             // chunks per halo pixel (odd)
+  static constexpr int SLOTS = (TYF + 2) * HC * PITCH; // halo chunks
   static constexpr int NQ = (SLOTS + 63) / 64;      // wave-sized copies per tile
   static constexpr int QPW = (NQ + 3) / 4;          // copies per wave (at most)
   static constexpr int NBUF = RPW > 1 ? 2 : 3;      // halo ring (two taller tiles fit 2 per CU)
@@ -178,15 +173,15 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
     for (int ks = 0; ks < KS; ks++) wf[ks] = *reinterpret_cast<const bf16x8*>(wr + 16 * ks);
   }
   // copy geometry of this lane: copy q of this wave fills slot (wave + 4 q) *
-  // 64 + lane = pixel p, physical chunk pc (logical chunk pc ^ key), packed as
-  // (halo row << 16 | halo column << 8 | logical chunk), -1 past the halo
-  // (recomputed per tile rather than held: it costs a few VALU per copy and
-  // no registers across the k loop)
+  // 64 + lane = pixel p, chunk c, packed as (halo row << 16 | halo column << 8
+  // | chunk), -1 for a pixel's padding chunk and past the halo (recomputed per
+  // tile rather than held: it costs a few VALU per copy and no registers
+  // across the k loop)
   auto geo = [&](int q) {
     const int g = wave + 4 * q, sl = g * 64 + lane;
     if (g >= NQ || sl >= F::SLOTS) return -1;
-    const int p = sl / CH, pc = sl % CH;
-    const int c = pc ^ ((p / (16 / CH)) % CH);
+    const int p = sl / F::PITCH, c = sl % F::PITCH;
+    if (c == CH) return -1;
     return ((p / HC) << 16) | ((p % HC) << 8) | c;
   };
   auto coords = [&](int tt, int& b, int& y0, int& x0) {
@@ -270,7 +265,7 @@ __global__ __launch_bounds__(kThreads, 2) void conv3x3_fwd(
 #pragma unroll
         for (int pb = 0; pb < NPB; pb++) {
           const int p = (wrow * RPW + rr + dy) * HC + 32 * (wpb * NPB + pb) + il + dx;
-          xf[slot][pb] = __builtin_bit_cast(bf16x8, halo[buf][halo_slot<CH>(p, 2 * c16 + kh)]);
+          xf[slot][pb] = __builtin_bit_cast(bf16x8, halo[buf][p * F::PITCH + 2 * c16 + kh]);
         }
       };
 #pragma unroll
