@@ -46,12 +46,13 @@ struct KindShape {
 // own register allocation.  Stencil tiles are 8 output rows x 256 columns for
 // windows up to 5 x 5 and 16 rows for 7 x 7, the one-problem kernel's choice.
 constexpr int kF32BK = 16;
+constexpr int kBf16BK = 64;  // bf16 slab depth: 64 k per barrier
 constexpr int kGemmOccupancy = 2;
 constexpr int stencil_rows(int k) { return k <= 5 ? 8 : 16; }
 const KindShape kShape[NUM_KINDS] = {
     {64, 64, kF32BK}, {64, 64, kF32BK}, {128, 64, kF32BK}, {128, 64, kF32BK},
     {64, 128, kF32BK}, {64, 128, kF32BK}, {128, 128, kF32BK}, {128, 128, kF32BK},
-    {64, 64, 32}, {64, 64, 32}, {128, 128, 32}, {128, 128, 32},
+    {64, 64, kBf16BK}, {64, 64, kBf16BK}, {128, 128, kBf16BK}, {128, 128, kBf16BK},
     {8, 256, 0}, {8, 256, 0}, {8, 256, 0}, {16, 256, 0},
     {8, 256, 0}, {8, 256, 0}, {8, 256, 0}, {16, 256, 0}};
 constexpr int kStencilClasses = NUM_KINDS - STENCIL_1;  // side x load width
@@ -80,7 +81,7 @@ constexpr int kGemmLdsBytes =
     cmax(cmax(cmax(4 * tiles::F32Cfg<128, 128, kF32BK, false, false>::LDS_FLOATS,
                    4 * tiles::F32Cfg<128, 128, kF32BK, false, true>::LDS_FLOATS),
               16 * tiles::F32AsyncCfg<128, 128, kF32Stages>::LDS_CHUNKS),
-         16 * tiles::Bf16Cfg<128, 128, 32>::LDS_CHUNKS);
+         16 * tiles::Bf16Cfg<128, 128, kBf16BK>::LDS_CHUNKS);
 static_assert(kGemmLdsBytes * kGemmOccupancy <= 160 * 1024, "LDS of the resident workgroups");
 
 // A descriptor address as a pointer into global memory: built from the integer
@@ -107,7 +108,7 @@ __device__ __noinline__ void item_f32(const Desc& d, int tm, int tn, char* lds) 
 }
 template <int BM, int BN, bool TB>
 __device__ __noinline__ void item_bf16(const Desc& d, int tm, int tn, char* lds) {
-  tiles::gemm_bf16_tile<BM, BN, 32, TB>(gptr<float>(d.out), d.ldc, gptr<const uint16_t>(d.a),
+  tiles::gemm_bf16_tile<BM, BN, kBf16BK, TB>(gptr<float>(d.out), d.ldc, gptr<const uint16_t>(d.a),
                                         d.lda, gptr<const uint16_t>(d.b), d.ldb, d.M, d.N, d.K,
                                         tm * BM, tn * BN, reinterpret_cast<i32x4*>(lds));
 }

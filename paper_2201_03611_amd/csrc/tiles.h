@@ -365,8 +365,31 @@ __device__ __forceinline__ void gemm_f32_async_tile(float* __restrict__ C, int64
 template <int BM, int BN, int BK>
 struct Bf16Cfg {
   static constexpr int CH = BK / 8;  // 16-byte chunks per slab row
-  static constexpr int LDS_CHUNKS = 2 * (BM + BN) * CH;
+  // B stored K x N sits in LDS as stored: BK rows of BN values, the row pitch
+  // padded by 64 bytes so the four rows one transposed read touches fall in
+  // four different quarters of a 256-byte bank line
+  static constexpr int BPITCH = BN * 2 + 64;  // bytes
+  static constexpr int B_KN_CHUNKS = 2 * BK * BPITCH / 16;
+  static constexpr int LDS_CHUNKS =
+      2 * BM * CH + (2 * BN * CH > B_KN_CHUNKS ? 2 * BN * CH : B_KN_CHUNKS);
 };
+
+// Four bf16 values of one column from four consecutive LDS rows (gfx950
+// ds_read_b64_tr_b16).  Within each group of 16 lanes, lane s supplies the
+// address of 4 consecutive 16-bit values M[s][0..3] and lane i receives
+// M[4 j + i / 4][i % 4] as element j: with lane s = 4 j + q pointing at
+// columns c0 + 4 q .. c0 + 4 q + 3 of row r0 + j, lane i receives column
+// c0 + i of rows r0 .. r0 + 3.
+typedef short s16x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ s16x4_t lds_read_tr16(const void* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef __attribute__((address_space(3))) s16x4_t lds_s16x4_t;
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4_t*)p);
+#else
+  (void)p;
+  return s16x4_t{0, 0, 0, 0};
+#endif
+}
 
 // row r, 16-byte chunk c -> LDS chunk index; the XOR key changes every 16/CH rows
 // so 16 consecutive rows at one logical chunk hit distinct slots of a 256-byte
@@ -431,12 +454,9 @@ __device__ __forceinline__ void gemm_bf16_tile(float* __restrict__ C, int64_t ld
       const int c = tid + kThreads * q;
       if (TB) {
         Bs[buf * BN * CH + swz16<CH>(c / CH, c % CH)] = rb[q];
-      } else {
+      } else {  // 8 consecutive n of row k, stored as they are
         const int k = c / (BN / 8), nc = (c % (BN / 8)) * 8;
-        uint16_t* bs = reinterpret_cast<uint16_t*>(Bs + buf * BN * CH);
-        const uint16_t* e = reinterpret_cast<const uint16_t*>(&rb[q]);
-#pragma unroll
-        for (int t = 0; t < 8; t++) bs[swz16<CH>(nc + t, k / 8) * 8 + (k % 8)] = e[t];
+        Bs[(buf * BK * T::BPITCH + k * T::BPITCH + nc * 2) / 16] = rb[q];
       }
     }
   };
@@ -466,9 +486,24 @@ __device__ __forceinline__ void gemm_bf16_tile(float* __restrict__ C, int64_t ld
 #pragma unroll
       for (int i = 0; i < TM; i++)
         a[i] = __builtin_bit_cast(bf16x8, As[cur * BM * CH + swz16<CH>(wm0 + 32 * i + il, c)]);
+      if (TB) {
 #pragma unroll
-      for (int j = 0; j < TN; j++)
-        b[j] = __builtin_bit_cast(bf16x8, Bs[cur * BN * CH + swz16<CH>(wn0 + 32 * j + il, c)]);
+        for (int j = 0; j < TN; j++)
+          b[j] = __builtin_bit_cast(bf16x8, Bs[cur * BN * CH + swz16<CH>(wn0 + 32 * j + il, c)]);
+      } else {
+        // lane (il, kh) needs column wn0 + 32 j + il at k = 16 ks + 8 kh .. + 7:
+        // two transposed reads of four rows each (see lds_read_tr16)
+        const int i16 = lane & 15, g16 = (lane >> 4) & 1;
+        const char* bsb = reinterpret_cast<const char*>(Bs) + cur * BK * T::BPITCH;
+        const int row = 16 * ks + 8 * kh + i16 / 4;
+#pragma unroll
+        for (int j = 0; j < TN; j++) {
+          const int col = wn0 + 32 * j + 16 * g16 + 4 * (i16 % 4);
+          const s16x4_t lo = lds_read_tr16(bsb + row * T::BPITCH + col * 2);
+          const s16x4_t hi = lds_read_tr16(bsb + (row + 4) * T::BPITCH + col * 2);
+          b[j] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+        }
+      }
 #pragma unroll
       for (int i = 0; i < TM; i++)
 #pragma unroll

@@ -139,7 +139,7 @@ def test_small_mixed_batch_and_graph_replays(rise):
     for i, p in enumerate(gemms):
         bm, bn, bk = plan.tile(i)
         # the persistent kernel's FP32 tiles are 16 deep in K, its bf16 tiles 32
-        assert bm in (64, 128) and bn in (64, 128) and bk == (32 if p["bf16"] else 16)
+        assert bm in (64, 128) and bn in (64, 128) and bk == (64 if p["bf16"] else 16)
     with pytest.raises(rise.RiseError, match="not a GEMM problem"):
         plan.tile(len(gemms))  # the first stencil
     with pytest.raises(rise.RiseError, match="outside the plan"):
