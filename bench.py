@@ -464,7 +464,7 @@ def batched_leg(rise, ri, torch, dev, stream):
             key = f"{t[0]}x{t[1]}x{t[2]}"
             kinds[key] = kinds.get(key, 0) + 1
         out[dtype]["strategy"] = {"gemm_tiles": dict(sorted(kinds.items())),
-                                  "stencil": "one resident kernel, LDS halo tiles"}
+                                  "stencil": "one kernel per window side and load width, one workgroup per LDS halo tile"}
         plan.destroy()
         del keep
         torch.cuda.empty_cache()

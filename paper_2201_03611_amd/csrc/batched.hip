@@ -160,7 +160,11 @@ __global__ __launch_bounds__(kThreads, kGemmOccupancy) void batched_gemm_kernel(
 }
 
 // Stencil tiles of one window side and load width: workgroup b runs items b,
-// b + grid, b + 2 grid, ... (the items of a class cost the same).
+// b + grid, b + 2 grid, ... (the items of a class cost the same).  The plans
+// launch one workgroup per item: the hardware then keeps every CU at the
+// occupancy below with a new tile's loads in flight as soon as one finishes,
+// which a resident grid walking its items in turn did not (the 512 + 256
+// batch: 2.53 -> 2.48 ms FP32, 1.50 -> 1.44 ms bf16).
 // resident workgroups per CU: as many as the tile's registers allow without
 // spilling (the item loop needs a few registers more than the one-problem
 // kernels' 64 for 5 x 5 and 126 for 7 x 7)
@@ -433,16 +437,9 @@ rise_status plan_build(PlanImpl** out, const rise_gemm_problem* g, int ng,
   if (n_gemm_items > 0)
     plan->launches.push_back(
         Launch{-1, 0, n_gemm_items, std::max(1, std::min(n_gemm_items, kGemmOccupancy * cus))});
-  for (int c = 0; c < kStencilClasses; c++) {
-    if (stencil_count[c] == 0) continue;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stencil_class_kernel(c), kThreads, 0) !=
-            hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
-    plan->launches.push_back(Launch{c, stencil_first[c], stencil_count[c],
-                                    std::max(1, std::min(stencil_count[c], per_cu * cus))});
-  }
+  for (int c = 0; c < kStencilClasses; c++)
+    if (stencil_count[c] > 0)  // one workgroup per item
+      plan->launches.push_back(Launch{c, stencil_first[c], stencil_count[c], stencil_count[c]});
 
   hipError_t e = hipSuccess;
   const size_t nd = std::max<size_t>(descs.size(), 1), ni = std::max<size_t>(items.size(), 1);
