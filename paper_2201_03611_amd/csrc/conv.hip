@@ -350,10 +350,13 @@ __global__ __launch_bounds__(kThreads) void conv3x3_dw(
     float* __restrict__ partial, const uint16_t* __restrict__ dout,
     const uint16_t* __restrict__ in, int B, int H, int W, int zero_pad, int tiles_x,
     int tiles_y, int ntiles) {
-  constexpr int NBLK = (CO / 32) * (TAPS * CI / 32);  // 32 x 32 blocks of dW^T
-  constexpr int PER_WAVE = (NBLK + 3) / 4;            // wave w owns blocks w, w + 4, ...
+  // dW^T is CO x 9 CI in 32 x 32 blocks: row blocks mb (output channels), column
+  // blocks nb (tap, input channel).  Wave w owns column blocks w, w + 4, ... for
+  // every row block, so each input fragment it reads feeds CO / 32 MFMAs
+  constexpr int MB = CO / 32;                         // row blocks
+  constexpr int NBC = TAPS * CI / 32;                 // column blocks
+  constexpr int PER_WAVE = (NBC + 3) / 4;             // column blocks per wave (at most)
   static_assert(CI % 32 == 0 && CO % 32 == 0, "channel counts");
-  static_assert(4 % (CO / 32) == 0, "a wave's blocks share one row block of dW^T");
   constexpr int PXT = WTY * TXP;                      // pixels per tile (128)
   constexpr int GS = CO + 8;                          // dOut pixel stride (16-bit values)
   constexpr int XS = CI + 8;                          // input pixel stride
@@ -370,11 +373,13 @@ __global__ __launch_bounds__(kThreads) void conv3x3_dw(
   // in which vertically neighbouring tiles (two shared halo rows) follow each other.
   const int run = (ntiles + gridDim.x - 1) / gridDim.x;
   const int t0 = blockIdx.x * run, t_end = min(ntiles, t0 + run);
-  f32x16 acc[PER_WAVE];
+  f32x16 acc[PER_WAVE][MB];
 #pragma unroll
   for (int q = 0; q < PER_WAVE; q++)
 #pragma unroll
-    for (int r = 0; r < 16; r++) acc[q][r] = 0.f;
+    for (int m = 0; m < MB; m++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[q][m][r] = 0.f;
 
   // All 16-byte loads of a tile are issued together (clamped addresses; a flag
   // says which values padding zeroes), one tile ahead: they are in flight
@@ -433,22 +438,21 @@ __global__ __launch_bounds__(kThreads) void conv3x3_dw(
     if (t + 1 < t_end) fetch(t + 1);
     __syncthreads();
     // K loop over the tile's pixels: 16 per step, rows r = 0..WTY-1, 64 pixels each
-    const int mb = wave % (CO / 32);  // the row block of dW^T all of this wave's blocks share
 #pragma unroll
     for (int ks = 0; ks < PXT / 16; ks++) {
       const int r = (16 * ks) / TXP;
       const int pb = (16 * ks) % TXP + src_px;  // this lane's source pixel in row r
-      bf16x8 av;
-      {
-        const uint16_t* pa = &go[(r * TXP + pb) * GS + 32 * mb + src_ch];
+      bf16x8 av[MB];
+#pragma unroll
+      for (int m = 0; m < MB; m++) {
+        const uint16_t* pa = &go[(r * TXP + pb) * GS + 32 * m + src_ch];
         const s16x4 lo = read_tr16(pa), hi = read_tr16(pa + 4 * GS);
-        av = __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+        av[m] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
       }
 #pragma unroll
       for (int q = 0; q < PER_WAVE; q++) {
-        const int blk = wave + 4 * q;
-        if (blk >= NBLK) break;  // wave-uniform
-        const int nb = blk / (CO / 32);
+        const int nb = wave + 4 * q;
+        if (nb >= NBC) break;  // wave-uniform
         const int n0 = 32 * nb;  // n = tap * CI + ci
         const int tap = n0 / CI, c0 = n0 - tap * CI;
         const int dy = tap / 3, dx = tap - dy * 3;
@@ -456,7 +460,9 @@ __global__ __launch_bounds__(kThreads) void conv3x3_dw(
         const s16x4 lo = read_tr16(pbv), hi = read_tr16(pbv + 4 * XS);
         const bf16x8 bv =
             __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[q], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < MB; m++)
+          acc[q][m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bv, acc[q][m], 0, 0, 0);
       }
     }
   }
@@ -464,15 +470,16 @@ __global__ __launch_bounds__(kThreads) void conv3x3_dw(
   float* dst = partial + (int64_t)blockIdx.x * CO * TAPS * CI;
 #pragma unroll
   for (int q = 0; q < PER_WAVE; q++) {
-    const int blk = wave + 4 * q;
-    if (blk >= NBLK) break;
-    const int mbq = blk % (CO / 32), nb = blk / (CO / 32);
+    const int nb = wave + 4 * q;
+    if (nb >= NBC) break;
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
-      const int o = 32 * mbq + 8 * (r >> 2) + 4 * kh + (r & 3);
-      const int n = 32 * nb + il;
-      dst[(int64_t)o * TAPS * CI + n] = acc[q][r];
-    }
+    for (int m = 0; m < MB; m++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int o = 32 * m + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int n = 32 * nb + il;
+        dst[(int64_t)o * TAPS * CI + n] = acc[q][m][r];
+      }
   }
 }
 
