@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <climits>
 
+#include "async_copy.h"
 #include "common.h"
 #include "tiles.h"
 
@@ -123,9 +124,7 @@ __device__ __align__(16) float g_stencil_zero_page[4];  // never written: zeros
 __device__ __align__(16) float g_stencil_dump_page[4];  // sink of out-of-image stores
 
 __device__ __forceinline__ void st_copy16_to_lds(const void* src, void* lds_base) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
-#endif
+  async::copy16(src, lds_base);
 }
 template <int N>
 __device__ __forceinline__ void st_wait_vmcnt() {
