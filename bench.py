@@ -349,8 +349,9 @@ def batched_plan(rise, ri, torch, dev, dtype):
     return plan, keep
 
 
-def event_ms(torch, stream, fn, reps):
-    fn()
+def event_ms(torch, stream, fn, reps, warm=3):
+    for _ in range(warm):
+        fn()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -429,8 +430,10 @@ def batched_leg(rise, ri, torch, dev, stream):
             p = gp[i]
             e = 4 if dtype == "f32" else 2
             gbytes += e * (p.M * p.K + p.K * p.N) + 4 * p.M * p.N
-        ms_graph = event_ms(torch, stream, lambda: plan.launch(stream), 10)
-        ms_direct = event_ms(torch, stream, lambda: plan.launch_direct(stream), 10)
+        # the first mode timed after the set-up ran 0.12-0.15 ms slower per launch
+        # with a single warm-up launch, whichever it was: warm up for 10
+        ms_graph = event_ms(torch, stream, lambda: plan.launch(stream), 10, warm=10)
+        ms_direct = event_ms(torch, stream, lambda: plan.launch_direct(stream), 10, warm=10)
 
         def separate():
             for i in range(512):

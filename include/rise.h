@@ -462,22 +462,25 @@ typedef struct {
 } rise_stencil_problem;
 
 /* A plan owns the device copy of the problem descriptors, the work-item list
- * (every output tile of every problem, largest estimated cost first) and a HIP
- * graph of  [reset the work counter] -> [one persistent kernel]  whose
- * workgroups take items until none are left.  The batch is the outer map of
- * the patterns: its items write distinct outputs, so any order is correct
- * (distinct output acceptors, paper Sec. V-C).  GEMM tile shapes come from a
- * per-tile cost table (tune_table: a file written by rise_autotune_batched, or
- * NULL for the built-in MI355X table).  plan_create allocates device memory and
- * synchronises; it is not meant for the hot path.  The problems' buffers must
- * stay valid for every launch of the plan. */
+ * (every output tile of every problem, GEMM tiles largest estimated cost first)
+ * and a HIP graph of  [reset the work counter] -> [one persistent GEMM kernel,
+ * whose workgroups take tiles from the counter until none are left] -> [one
+ * stencil kernel per window side and load width, one workgroup per tile].
+ * Launches of one plan share its work counter, so they must not overlap:
+ * issue them on one stream, or order them with events.  The batch is the
+ * outer map of the patterns: its items write distinct outputs, so any order
+ * is correct (distinct output acceptors, paper Sec. V-C).  GEMM tile shapes
+ * come from a per-tile cost table (tune_table: a file written by
+ * rise_autotune_batched, or NULL for the built-in MI355X table).  plan_create
+ * allocates device memory and synchronises; it is not meant for the hot path.
+ * The problems' buffers must stay valid for every launch of the plan. */
 typedef struct rise_plan rise_plan;
 rise_status rise_plan_create(rise_plan** plan, const rise_gemm_problem* gemms, int32_t n_gemm,
                              const rise_stencil_problem* stencils, int32_t n_stencil,
                              const char* tune_table, void* stream);
 /* One launch of the captured graph on `stream`. */
 rise_status rise_plan_launch(rise_plan* plan, void* stream);
-/* The same two kernels launched directly (no graph), for comparison. */
+/* The same kernels launched directly (no graph), for comparison. */
 rise_status rise_plan_launch_direct(rise_plan* plan, void* stream);
 rise_status rise_plan_destroy(rise_plan* plan);
 /* Number of work items; the tile (bm, bn, bk) chosen for GEMM `problem`. */
