@@ -166,9 +166,10 @@ __global__ __launch_bounds__(kThreads, kGemmOccupancy) void batched_gemm_kernel(
 // which a resident grid walking its items in turn did not (the 512 + 256
 // batch: 2.53 -> 2.48 ms FP32, 1.50 -> 1.44 ms bf16).
 // resident workgroups per CU: as many as the tile's registers allow without
-// spilling (the item loop needs a few registers more than the one-problem
-// kernels' 64 for 5 x 5 and 126 for 7 x 7)
-constexpr int stencil_occupancy(int k) { return k <= 3 ? 8 : k == 5 ? 5 : 3; }
+// spilling; the window of 5 x 5 and 7 x 7 tiles streams through registers a
+// row at a time (44-49 and 75-80 VGPRs with the item loop, against 78-83 and
+// 143-151 holding the whole window), and 7 x 7 is held to six by its 23 KB of LDS
+constexpr int stencil_occupancy(int k) { return k <= 5 ? 8 : 6; }
 
 template <int K, bool VEC>
 __global__ __launch_bounds__(kThreads, stencil_occupancy(K)) void batched_stencil_kernel(const Desc* __restrict__ descs,
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(kThreads, stencil_occupancy(K)) void batched_stenci
     const int tile = __builtin_amdgcn_readfirstlane(items[i].tile);
     const Desc& d = descs[desc];
     const int tm = tile / d.tiles_n, tn = tile - tm * d.tiles_n;
-    tiles::stencil_lds_tile<K, VEC, TY, true, true>(
+    tiles::stencil_lds_tile<K, VEC, TY, true, true, (K >= 5)>(
         gptr<float>(d.out), d.ldc, gptr<const float>(d.a), d.lda, d.M, d.N, gptr<const float>(d.b),
         d.zero_pad, tm * TY, tn * tiles::kStencilTX, lds);
     __syncthreads();  // every wave is done with the LDS tile before the next item fills it

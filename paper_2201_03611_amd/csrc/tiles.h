@@ -668,47 +668,80 @@ __device__ __forceinline__ void stencil_stash_aligned(const StencilRegs<K, TY>& 
 
 // LDS -> k*k weighted sums.  Wave v computes output rows [y0 + v*TY/4,
 // y0 + (v+1)*TY/4); lane l owns columns x0 + 4l .. x0 + 4l + 3.
+// The window rows stream through registers: row j feeds every output row o
+// with 0 <= j - o < k, so each output takes its k*k products in the order dy
+// outer, dx inner.  ROWWISE (the default for k >= 7; the batched kernels take
+// it from k = 5, to fit eight workgroups per CU) keeps that streaming in
+// the schedule: the next row's LDS reads are issued before this row's FMAs,
+// and empty asm statements after the FMAs take the accumulators and the LDS
+// row index as operands they may change, so the FMAs must be done before them
+// and the reads two rows on cannot be hoisted above them; two window rows and
+// the accumulators are live instead of the whole window (k = 7 on 16-row
+// tiles: 43 VGPRs instead of 124).
 // EDGES (clamp padding with whole 16-byte chunks): the chunk left of column 0
 // (lane 0 when `left`) and every chunk right of column lim - 1 (lim is the
 // image width on the right-edge tile) read as the edge element, whatever the
 // LDS tile holds there.
-template <int K, int TY, bool EDGES = false>
+template <int K, int TY, bool EDGES = false, bool ROWWISE = (K >= 7)>
 __device__ __forceinline__ void stencil_compute(float (&res)[TY / 4][4], const float (&wt)[K][K],
                                                 const f32x4* lds, bool left = false,
                                                 int lim = 0, int x = 0) {
   constexpr int R = (K - 1) / 2;
-  constexpr int RW = TY / 4;  // output rows per wave
-  auto tile = reinterpret_cast<const f32x4(*)[kLChunks]>(lds);
+  constexpr int RW = TY / 4;      // output rows per wave
+  constexpr int NR = RW + 2 * R;  // window rows
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = wave * RW;
+  // this lane's chunk of window row 0 (an index, so the pin below leaves the
+  // pointer's LDS address space known); row j is kLChunks * j chunks further
+  int base = wave * RW * kLChunks + lane;
   // LDS chunk `lane` = columns x-4..x-1, lane+1 = x..x+3, lane+2 = x+4..x+7
-  float win[RW + 2 * R][12];
-#pragma unroll
-  for (int j = 0; j < RW + 2 * R; j++) {
-    f32x4 c1 = tile[r0 + j][lane + 1];
-    win[j][4] = c1.x; win[j][5] = c1.y; win[j][6] = c1.z; win[j][7] = c1.w;
+  auto load_row = [&](int j, f32x4 (&c)[3]) {
+    const f32x4* row = lds + base + j * kLChunks;
+    c[1] = row[1];
     if (R > 0) {
-      f32x4 c0 = tile[r0 + j][lane];
-      f32x4 c2 = tile[r0 + j][lane + 2];
+      c[0] = row[0];
+      c[2] = row[2];
       if (EDGES) {
-        if (left && lane == 0) c0 = f32x4{c1.x, c1.x, c1.x, c1.x};
-        if (x + 4 >= lim) c2 = f32x4{c1.w, c1.w, c1.w, c1.w};
+        if (left && lane == 0) c[0] = f32x4{c[1].x, c[1].x, c[1].x, c[1].x};
+        if (x + 4 >= lim) c[2] = f32x4{c[1].w, c[1].w, c[1].w, c[1].w};
       }
-      win[j][0] = c0.x; win[j][1] = c0.y; win[j][2] = c0.z; win[j][3] = c0.w;
-      win[j][8] = c2.x; win[j][9] = c2.y; win[j][10] = c2.z; win[j][11] = c2.w;
+    } else {
+      c[0] = c[2] = c[1];
     }
-  }
+  };
 #pragma unroll
   for (int o = 0; o < RW; o++)
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      float a = 0.f;
+    for (int q = 0; q < 4; q++) res[o][q] = 0.f;
+  f32x4 cur[3], nxt[3];
+  load_row(0, cur);
 #pragma unroll
-      for (int dy = 0; dy < K; dy++)
+  for (int j = 0; j < NR; j++) {
+    if (j + 1 < NR) load_row(j + 1, nxt);
+    float win[12];
 #pragma unroll
-        for (int dx = 0; dx < K; dx++) a = fmaf(win[o + dy][4 + q + dx - R], wt[dy][dx], a);
-      res[o][q] = a;
+    for (int c = 0; c < 3; c++) {
+      win[4 * c] = cur[c].x; win[4 * c + 1] = cur[c].y;
+      win[4 * c + 2] = cur[c].z; win[4 * c + 3] = cur[c].w;
     }
+#pragma unroll
+    for (int o = 0; o < RW; o++) {
+      const int dy = j - o;
+      if (dy < 0 || dy >= K) continue;
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int dx = 0; dx < K; dx++)
+          res[o][q] = fmaf(win[4 + q + dx - R], wt[dy][dx], res[o][q]);
+    }
+    if (ROWWISE) {  // volatile asm statements keep their order: accumulators, then the index
+#pragma unroll
+      for (int o = 0; o < RW; o++)
+        asm volatile("" : "+v"(res[o][0]), "+v"(res[o][1]), "+v"(res[o][2]), "+v"(res[o][3]));
+      asm volatile("" : "+v"(base));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) cur[c] = nxt[c];
+  }
 }
 
 // join: 16-byte row stores of the wave's outputs (guarded at the image edge;
@@ -749,12 +782,12 @@ __device__ __forceinline__ void stencil_store(float* __restrict__ out, int64_t l
   }
 }
 
-template <int K, bool VEC, int TY, bool NT>
+template <int K, bool VEC, int TY, bool NT, bool ROWWISE = (K >= 7)>
 __device__ __forceinline__ void stencil_compute_store(float* __restrict__ out, int64_t ld_out,
                                                       int H, int W, const float (&wt)[K][K],
                                                       int y0, int x0, const f32x4* lds) {
   float res[TY / 4][4];
-  stencil_compute<K, TY>(res, wt, lds);
+  stencil_compute<K, TY, false, ROWWISE>(res, wt, lds);
   stencil_store<VEC, TY, NT>(out, ld_out, H, W, res, y0, x0);
 }
 
@@ -777,7 +810,8 @@ __device__ __forceinline__ void stencil_weights(float (&wt)[K][K], const float* 
 // One tile, start to finish (fetch, stage, barrier, compute, store).
 // NT: non-temporal output stores (the output is not read again soon); without
 // it the output stays in the caches for a consumer that reads it next.
-template <int K, bool VEC, int TY, bool NT = true, bool SCALAR_W = false>
+template <int K, bool VEC, int TY, bool NT = true, bool SCALAR_W = false,
+          bool ROWWISE = (K >= 7)>
 __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_t ld_out,
                                                  const float* __restrict__ in, int64_t ld_in,
                                                  int H, int W, const float* __restrict__ w,
@@ -806,7 +840,7 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
   __syncthreads();
   float wt[K][K];
   stencil_weights<K, SCALAR_W>(wt, w);
-  stencil_compute_store<K, VEC, TY, NT>(out, ld_out, H, W, wt, y0, x0, lds);
+  stencil_compute_store<K, VEC, TY, NT, ROWWISE>(out, ld_out, H, W, wt, y0, x0, lds);
 }
 
 }  // namespace tiles

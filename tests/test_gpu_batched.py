@@ -171,6 +171,35 @@ def test_f32_tiles_both_schedules(rise):
     plan.destroy()
 
 
+def test_bf16_items_ragged(rise):
+    # bf16 GEMMs with M and N ragged against the 64 and 128 tiles and K a
+    # multiple of 8 that is not a whole number of 64-k slabs (zero-filled chunks)
+    import torch
+
+    g = ri.rng(4242)
+    sizes = [(70, 136, 96), (200, 72, 64), (130, 264, 288), (64, 64, 32),
+             (50, 72, 40), (130, 200, 200), (257, 136, 72), (33, 8, 264)]
+    gemms = []
+    for opB in (0, 1):
+        for M, N, K in sizes:
+            gemms.append(dict(M=M, N=N, K=K, opB=opB, A=ri.uniform_matrix(g, M, K),
+                              B=ri.uniform_matrix(g, K, N), bf16=True))
+    gp, sp, keep = to_device(rise, gemms, [])
+    print(f"batch: {len(gemms)} bf16 gemms", flush=True)
+    plan = rise.Plan(gp, len(gemms), sp, 0)
+    for rep in range(2):
+        for p in gemms:
+            p["dC"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for p in gemms:
+            check_gemm(p, host(p["dC"]))
+    for i in range(len(gemms)):
+        assert plan.tile(i)[2] == 64
+    plan.destroy()
+
+
 def test_batched_equals_single_calls(rise):
     import torch
 
