@@ -792,19 +792,18 @@ __device__ __forceinline__ void stencil_compute_store(float* __restrict__ out, i
 }
 
 // SCALAR: the weight pointer is read from memory (not a kernel argument), so
-// the compiler cannot tell it is the same for every lane; the values are moved
-// to scalar registers explicitly instead of occupying k*k vector registers.
+// the compiler cannot tell that the loads are uniform and not overwritten while
+// the kernel runs; it would read them with vector loads.  They are read through
+// the constant address space instead: scalar loads straight into scalar
+// registers (the weights are the same for every lane and only read).
 template <int K, bool SCALAR = false>
 __device__ __forceinline__ void stencil_weights(float (&wt)[K][K], const float* __restrict__ w) {
+  typedef const __attribute__((address_space(4))) float cfloat;
+  cfloat* cw = (cfloat*)(uintptr_t)w;
 #pragma unroll
   for (int dy = 0; dy < K; dy++)
 #pragma unroll
-    for (int dx = 0; dx < K; dx++) {
-      const float v = w[dy * K + dx];
-      wt[dy][dx] = SCALAR ? __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                          __builtin_bit_cast(int, v)))
-                          : v;
-    }
+    for (int dx = 0; dx < K; dx++) wt[dy][dx] = SCALAR ? cw[dy * K + dx] : w[dy * K + dx];
 }
 
 // One tile, start to finish (fetch, stage, barrier, compute, store).
@@ -818,6 +817,8 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
                                                  int zero_pad, int y0, int x0, f32x4* lds) {
   StencilRegs<K, TY> st;
   using Cfg = StencilCfg<K, TY>;
+  float wt[K][K];
+  if (SCALAR_W) stencil_weights<K, true>(wt, w);  // scalar loads, in flight during the fetch
   if (VEC && y0 >= Cfg::R && y0 + TY + Cfg::R <= H && x0 >= kHalo &&
       x0 + kStencilTX + kHalo <= W) {
     // interior tile: no padding, every chunk at a fixed offset from the corner
@@ -838,8 +839,7 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
     stencil_stash<K, TY>(st, lds);
   }
   __syncthreads();
-  float wt[K][K];
-  stencil_weights<K, SCALAR_W>(wt, w);
+  if (!SCALAR_W) stencil_weights<K, false>(wt, w);
   stencil_compute_store<K, VEC, TY, NT, ROWWISE>(out, ld_out, H, W, wt, y0, x0, lds);
 }
 
