@@ -819,15 +819,16 @@ __device__ __forceinline__ void stencil_lds_tile(float* __restrict__ out, int64_
   using Cfg = StencilCfg<K, TY>;
   float wt[K][K];
   if (SCALAR_W) stencil_weights<K, true>(wt, w);  // scalar loads, in flight during the fetch
-  if (VEC && y0 >= Cfg::R && y0 + TY + Cfg::R <= H && x0 >= kHalo &&
-      x0 + kStencilTX + kHalo <= W) {
+  if (y0 >= Cfg::R && y0 + TY + Cfg::R <= H && x0 >= kHalo && x0 + kStencilTX + kHalo <= W) {
     // interior tile: no padding, every chunk at a fixed offset from the corner
+    // (16-byte aligned when VEC, otherwise at the rows' own 4-byte alignment)
     const float* corner = in + (int64_t)(y0 - Cfg::R) * ld_in + (x0 - kHalo);
 #pragma unroll
     for (int p = 0; p < Cfg::PER; p++) {
       const int c = min((int)threadIdx.x + p * kThreads, Cfg::LDS_CHUNKS - 1);
       const int lr = c / kLChunks, cc = c - lr * kLChunks;
-      st[p] = *reinterpret_cast<const f32x4*>(corner + (int64_t)lr * ld_in + 4 * cc);
+      const float* q = corner + (int64_t)lr * ld_in + 4 * cc;
+      st[p] = VEC ? *reinterpret_cast<const f32x4*>(q) : f32x4(*reinterpret_cast<const f32x4u*>(q));
     }
     stencil_stash<K, TY>(st, lds);
   } else if (VEC && (W & 3) == 0) {
