@@ -53,8 +53,9 @@ const KindShape kShape[NUM_KINDS] = {
     {64, 64, kF32BK}, {64, 64, kF32BK}, {128, 64, kF32BK}, {128, 64, kF32BK},
     {64, 128, kF32BK}, {64, 128, kF32BK}, {128, 128, kF32BK}, {128, 128, kF32BK},
     {64, 64, kBf16BK}, {64, 64, kBf16BK}, {128, 128, kBf16BK}, {128, 128, kBf16BK},
-    {8, 256, 0}, {8, 256, 0}, {8, 256, 0}, {16, 256, 0},
-    {8, 256, 0}, {8, 256, 0}, {8, 256, 0}, {16, 256, 0}};
+    {stencil_rows(1), 256, 0}, {stencil_rows(3), 256, 0}, {stencil_rows(5), 256, 0},
+    {stencil_rows(7), 256, 0},  {stencil_rows(1), 256, 0}, {stencil_rows(3), 256, 0},
+    {stencil_rows(5), 256, 0},  {stencil_rows(7), 256, 0}};
 constexpr int kStencilClasses = NUM_KINDS - STENCIL_1;  // side x load width
 
 struct Desc {  // one problem; device addresses as integers (see gptr)
