@@ -413,9 +413,9 @@ rise_status rise_set_tune_cache(const char* path);
 /* ------------------------------------------------------------------------ */
 
 /* A streaming device copy of `bytes` (a multiple of 16; 16-byte aligned,
- * non-overlapping device buffers): 16-byte loads, non-temporal 16-byte
- * stores.  Timed over >= 2 GiB it gives the HBM bandwidth a kernel can reach
- * (read + write bytes / time). */
+ * non-overlapping device buffers): one 16-byte load and store per thread,
+ * workgroup b copying the 4 KB block b in one pass.  Timed over >= 2 GiB it
+ * gives the HBM bandwidth a kernel can reach (read + write bytes / time). */
 rise_status rise_ceiling_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /* Back-to-back matrix instructions on every SIMD (four waves per SIMD, four

