@@ -118,6 +118,111 @@ __global__ __launch_bounds__(kThreads) void iterate_sum_pass(
   for (int o = tid; o < qv; o += kThreads) dst[g0 + o] = lds[swz(from + o)];
 }
 
+// Fan-ins 3 to 8, passes of at least one round: the first round runs in
+// registers straight from the loads, each thread folding whole groups of N
+// neighbours, so LDS holds one value per group (never the raw chunk) and the
+// later rounds run there as in iterate_sum_pass.  With an aligned chunk a
+// thread loads a unit of the fewest consecutive groups that stays 16-byte
+// aligned (one group for N = 4 and 8, two for 6, four for odd N) with 16-byte
+// loads; the groups past the last whole unit, and unaligned chunks, load value
+// by value.  The LDS tile is a sixth of iterate_sum_pass's or less, so eight
+// workgroups share a CU instead of three and their loads overlap the other
+// workgroups' LDS rounds.  The sums are the same left folds from 0, in the
+// same order.
+template <int N>
+__global__ __launch_bounds__(kThreads) void iterate_sum_pass_first(
+    float* __restrict__ dst, const float* __restrict__ src, int64_t len_out, int L, int G, int q,
+    int vec) {
+  constexpr int kA = (kChunk / N + 63) / 64 * 64;      // round-1 outputs (whole swizzle blocks)
+  constexpr int kB = (kChunk / N / N + 63) / 64 * 64;  // round-2 outputs
+  __shared__ float lds[kA + kB];
+  const int tid = threadIdx.x;
+  const int64_t g0 = (int64_t)blockIdx.x * q;
+  const int qv = (int)(len_out - g0 < q ? len_out - g0 : q);
+  const int C1 = qv * (G / N);  // groups of the first round in this chunk
+  const float* s = src + g0 * G;
+  if (vec) {
+    constexpr int UG = N % 4 == 0 ? 1 : N % 2 == 0 ? 2 : 4;  // groups per 16-byte-aligned unit
+    constexpr int UV = UG * N / 4;                           // 16-byte loads per unit
+    constexpr int kU = (kChunk / N / UG + kThreads - 1) / kThreads;  // units per thread
+    const int nu = C1 / UG;
+    float4 x[kU][UV];
+#pragma unroll
+    for (int i = 0; i < kU; i++) {
+      const int u = tid + i * kThreads;
+#pragma unroll
+      for (int j = 0; j < UV; j++)
+        x[i][j] = u < nu ? reinterpret_cast<const float4*>(s)[(int64_t)u * UV + j]
+                         : float4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < kU; i++) {
+      const int u = tid + i * kThreads;
+      if (u < nu) {
+        float f[4 * UV];
+#pragma unroll
+        for (int j = 0; j < UV; j++) {
+          f[4 * j] = x[i][j].x;
+          f[4 * j + 1] = x[i][j].y;
+          f[4 * j + 2] = x[i][j].z;
+          f[4 * j + 3] = x[i][j].w;
+        }
+#pragma unroll
+        for (int g = 0; g < UG; g++) {
+          float acc = 0.f;
+#pragma unroll
+          for (int j = 0; j < N; j++) acc = acc + f[g * N + j];
+          lds[swz(UG * u + g)] = acc;
+        }
+      }
+    }
+    const int o = UG * nu + tid;  // groups past the last whole unit
+    if (o < C1) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; j++) acc = acc + s[(int64_t)o * N + j];
+      lds[swz(o)] = acc;
+    }
+  } else {
+    constexpr int kGr = (kChunk / N + kThreads - 1) / kThreads;  // groups per thread
+    float x[kGr][N];
+#pragma unroll
+    for (int i = 0; i < kGr; i++) {
+      const int o = tid + i * kThreads;
+#pragma unroll
+      for (int j = 0; j < N; j++) x[i][j] = o < C1 ? s[(int64_t)o * N + j] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < kGr; i++) {
+      const int o = tid + i * kThreads;
+      if (o < C1) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < N; j++) acc = acc + x[i][j];
+        lds[swz(o)] = acc;
+      }
+    }
+  }
+  int len = C1, from = 0, to = kA;
+  for (int round = 1; round < L; round++) {
+    __syncthreads();
+    const int lo = len / N;
+    for (int o = tid; o < lo; o += kThreads) {
+      const int b = from + o * N;
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; j++) acc = acc + lds[swz(b + j)];
+      lds[swz(to + o)] = acc;
+    }
+    len = lo;
+    const int t = from;
+    from = to;
+    to = t;
+  }
+  __syncthreads();
+  for (int o = tid; o < qv; o += kThreads) dst[g0 + o] = lds[swz(from + o)];
+}
+
 // Binary tree (n = 2), 16-byte aligned chunk, L >= 2 rounds: rounds 1-2 fold
 // each 16-byte load in registers; the next rounds pair neighbouring lanes of a
 // wavefront (lanes hold consecutive positions, so an exchange with lane t ^ 2^j
@@ -257,9 +362,31 @@ rise_status launch_iterate_sum(float* out, const float* in, int64_t n, int64_t m
     // multiple of 4 and the source is
     const bool vec = ((uintptr_t)src & 15) == 0 && ((int64_t)p.q * p.G) % 4 == 0;
     const int a = vec ? p.a : 0, R = vec ? p.R : 1;
+    const dim3 grid((unsigned)p.blocks), block(kThreads);
+    const int v = vec ? 1 : 0;
     if (n == 2 && vec && p.L >= 2)
-      hipLaunchKernelGGL(iterate_sum_pass_bin, dim3((unsigned)p.blocks), dim3(kThreads), 0, s,
-                         dst, src, p.len_out, p.L, p.q);
+      hipLaunchKernelGGL(iterate_sum_pass_bin, grid, block, 0, s, dst, src, p.len_out, p.L, p.q);
+    else if (p.L < 1)  // k = 0: a copy
+      hipLaunchKernelGGL(iterate_sum_pass, grid, block, 0, s, dst, src, p.len_out, (int)n, p.L,
+                         p.G, p.q, a, R, v);
+    else if (n == 3)
+      hipLaunchKernelGGL(iterate_sum_pass_first<3>, grid, block, 0, s, dst, src, p.len_out, p.L,
+                         p.G, p.q, v);
+    else if (n == 4)
+      hipLaunchKernelGGL(iterate_sum_pass_first<4>, grid, block, 0, s, dst, src, p.len_out, p.L,
+                         p.G, p.q, v);
+    else if (n == 5)
+      hipLaunchKernelGGL(iterate_sum_pass_first<5>, grid, block, 0, s, dst, src, p.len_out, p.L,
+                         p.G, p.q, v);
+    else if (n == 6)
+      hipLaunchKernelGGL(iterate_sum_pass_first<6>, grid, block, 0, s, dst, src, p.len_out, p.L,
+                         p.G, p.q, v);
+    else if (n == 7)
+      hipLaunchKernelGGL(iterate_sum_pass_first<7>, grid, block, 0, s, dst, src, p.len_out, p.L,
+                         p.G, p.q, v);
+    else if (n == 8)
+      hipLaunchKernelGGL(iterate_sum_pass_first<8>, grid, block, 0, s, dst, src, p.len_out, p.L,
+                         p.G, p.q, v);
     else
       hipLaunchKernelGGL(iterate_sum_pass, dim3((unsigned)p.blocks), dim3(kThreads), 0, s, dst,
                          src, p.len_out, (int)n, p.L, p.G, p.q, a, R, vec ? 1 : 0);

@@ -62,6 +62,15 @@ CASES = [
     (16, 2, 5),
     (5, 1, 1),
     (7, 9, 4),
+    (3, 4096, 2),    # 910 groups of 9 per workgroup (chunks not 16-byte aligned)
+    (3, 8, 3),       # one aligned chunk of 8 groups of 27: 16-byte loads of 4 groups of 3
+    (6, 500, 2),     # aligned chunks of 1362 first-round groups: 16-byte loads + 2-group tail
+    (6, 4001, 1),    # one round per pass, ragged last workgroup
+    (8, 1000, 3),    # 16 groups of 512 per workgroup, three rounds
+    (8, 1027, 1),    # one round; the last workgroup holds 3 groups (tail only)
+    (5, 3, 5),       # 5^5 per group, one group per workgroup
+    (4, 1001, 2),    # fan-in 4 with 16-value groups, ragged last workgroup
+    (4, 2051, 1),    # one round; the last workgroup holds 3 groups (tail only)
     (4097, 3, 1),    # one group per workgroup
     (8192, 2, 1),    # the largest fan-in
 ]
