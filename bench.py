@@ -538,11 +538,13 @@ def stencil_iterate_leg(rise, ri, torch, dev, stream):
 def iterate_leg(rise, torch, dev, stream):
     """iterate with the tree-reduction body (binary tree, n = 2) over 2^26 FP32
     values (256 MiB, read once) to one sum, and over 4096 rows of 2^14 values
-    to 4096 sums: HBM GB/s of the input read against the 8 TB/s peak.  The
-    launches rotate over three inputs (768 MiB, above the 256 MB last-level
-    cache), so every launch reads its input from HBM."""
+    to 4096 sums; fan-ins 3 (2 x 3^16 values) and 8 (4 x 8^8 values): HBM GB/s
+    of the input read against the 8 TB/s peak.  The launches rotate over three
+    inputs (above the 256 MB last-level cache), so every launch reads its input
+    from HBM."""
     res = {}
-    for name, n, m, k in (("tree_2pow26_to_1", 2, 1, 26), ("rows_4096x2pow14", 2, 4096, 14)):
+    for name, n, m, k in (("tree_2pow26_to_1", 2, 1, 26), ("rows_4096x2pow14", 2, 4096, 14),
+                          ("fanin3_2x3pow16", 3, 2, 16), ("fanin8_4x8pow8", 8, 4, 8)):
         total = m * n ** k
         g = torch.Generator(device=dev)
         g.manual_seed(1300)
