@@ -125,10 +125,40 @@ __global__ __launch_bounds__(kThreads) void iterate_sum_pass(
 // thread loads a unit of the fewest consecutive groups that stays 16-byte
 // aligned (one group for N = 4 and 8, two for 6, four for odd N) with 16-byte
 // loads; the groups past the last whole unit, and unaligned chunks, load value
-// by value.  The LDS tile is a sixth of iterate_sum_pass's or less, so eight
+// by value (in 4-byte-aligned loads of up to 16 bytes).  The LDS tile is a sixth of iterate_sum_pass's or less, so eight
 // workgroups share a CU instead of three and their loads overlap the other
 // workgroups' LDS rounds.  The sums are the same left folds from 0, in the
 // same order.
+// The N values of one group from a 4-byte-aligned address, in loads of up to
+// 16 bytes that need only 4-byte alignment (N = 3: one 12-byte load).
+typedef float f32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f32x3_a4 __attribute__((ext_vector_type(3), aligned(4)));
+typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+template <int N>
+__device__ __forceinline__ void load_group(float (&v)[N], const float* p) {
+#pragma unroll
+  for (int j = 0; j + 4 <= N; j += 4) {
+    const f32x4_a4 t = *reinterpret_cast<const f32x4_a4*>(p + j);
+    v[j] = t.x;
+    v[j + 1] = t.y;
+    v[j + 2] = t.z;
+    v[j + 3] = t.w;
+  }
+  constexpr int j = N / 4 * 4;
+  if constexpr (N - j == 3) {
+    const f32x3_a4 t = *reinterpret_cast<const f32x3_a4*>(p + j);
+    v[j] = t.x;
+    v[j + 1] = t.y;
+    v[j + 2] = t.z;
+  } else if constexpr (N - j == 2) {
+    const f32x2_a4 t = *reinterpret_cast<const f32x2_a4*>(p + j);
+    v[j] = t.x;
+    v[j + 1] = t.y;
+  } else if constexpr (N - j == 1) {
+    v[j] = p[j];
+  }
+}
+
 template <int N>
 __global__ __launch_bounds__(kThreads) void iterate_sum_pass_first(
     float* __restrict__ dst, const float* __restrict__ src, int64_t len_out, int L, int G, int q,
@@ -189,8 +219,12 @@ __global__ __launch_bounds__(kThreads) void iterate_sum_pass_first(
 #pragma unroll
     for (int i = 0; i < kGr; i++) {
       const int o = tid + i * kThreads;
+      if (o < C1) {
+        load_group<N>(x[i], s + (int64_t)o * N);
+      } else {
 #pragma unroll
-      for (int j = 0; j < N; j++) x[i][j] = o < C1 ? s[(int64_t)o * N + j] : 0.f;
+        for (int j = 0; j < N; j++) x[i][j] = 0.f;
+      }
     }
 #pragma unroll
     for (int i = 0; i < kGr; i++) {
