@@ -51,7 +51,8 @@ def parse():
     p.add_argument("--only", default=None,
                    choices=["gemm_f32", "gemm_bf16", "gemm_bf16x3", "gemm_fp8", "stencil",
                             "conv_fwd", "conv_bwd", "batched", "gemv", "gemv_t", "iterate_sum",
-                            "stencil_iterate", "stencil_iterate_1"],
+                            "iterate_sum_fanin3", "iterate_sum_fanin8", "stencil_iterate",
+                            "stencil_iterate_1"],
                    help="run one kernel of the path --reps times (for profilers) and exit")
     p.add_argument("--reps", type=int, default=5)
     return p.parse_args()
@@ -297,6 +298,13 @@ def run_only(what, reps, rise, ri, torch, dev, stream):
         ws = torch.empty(max(rise.rise_iterate_sum_workspace(2, 1, 26), 1), device=dev,
                          dtype=torch.uint8)
         call = lambda i: rise.rise_iterate_sum(out, x, 2, 1, 26, ws=ws, stream=stream)
+    elif what in ("iterate_sum_fanin3", "iterate_sum_fanin8"):
+        n, m, k = (3, 2, 16) if what.endswith("3") else (8, 4, 8)
+        x = torch.rand((m * n ** k,), device=dev, generator=g) * 2 - 1
+        out = torch.empty(m, device=dev)
+        ws = torch.empty(max(rise.rise_iterate_sum_workspace(n, m, k), 1), device=dev,
+                         dtype=torch.uint8)
+        call = lambda i: rise.rise_iterate_sum(out, x, n, m, k, ws=ws, stream=stream)
     else:  # batched
         plan, keep = batched_plan(rise, ri, torch, dev, "f32")
         call = lambda i: plan.launch(stream)
