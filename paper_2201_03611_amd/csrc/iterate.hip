@@ -118,17 +118,6 @@ __global__ __launch_bounds__(kThreads) void iterate_sum_pass(
   for (int o = tid; o < qv; o += kThreads) dst[g0 + o] = lds[swz(from + o)];
 }
 
-// Fan-ins 3 to 8, passes of at least one round: the first round runs in
-// registers straight from the loads, each thread folding whole groups of N
-// neighbours, so LDS holds one value per group (never the raw chunk) and the
-// later rounds run there as in iterate_sum_pass.  With an aligned chunk a
-// thread loads a unit of the fewest consecutive groups that stays 16-byte
-// aligned (one group for N = 4 and 8, two for 6, four for odd N) with 16-byte
-// loads; the groups past the last whole unit, and unaligned chunks, load value
-// by value (in 4-byte-aligned loads of up to 16 bytes).  The LDS tile is a sixth of iterate_sum_pass's or less, so eight
-// workgroups share a CU instead of three and their loads overlap the other
-// workgroups' LDS rounds.  The sums are the same left folds from 0, in the
-// same order.
 // The N values of one group from a 4-byte-aligned address, in loads of up to
 // 16 bytes that need only 4-byte alignment (N = 3: one 12-byte load).
 typedef float f32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
@@ -159,6 +148,18 @@ __device__ __forceinline__ void load_group(float (&v)[N], const float* p) {
   }
 }
 
+// Fan-ins 3 to 8, passes of at least one round: the first round runs in
+// registers straight from the loads, each thread folding whole groups of N
+// neighbours, so LDS holds one value per group (never the raw chunk) and the
+// later rounds run there as in iterate_sum_pass.  With an aligned chunk a
+// thread loads a unit of the fewest consecutive groups that stays 16-byte
+// aligned (one group for N = 4 and 8, two for 6, four for odd N) with 16-byte
+// loads; the groups past the last whole unit, unaligned chunks and every chunk
+// for N = 6 (whose two-group units measured slower) load group by group in
+// 4-byte-aligned loads of up to 16 bytes.  The LDS tile is a sixth of
+// iterate_sum_pass's or less, so eight workgroups share a CU instead of three
+// and their loads overlap the other workgroups' LDS rounds.  The sums are the
+// same left folds from 0, in the same order.
 template <int N>
 __global__ __launch_bounds__(kThreads) void iterate_sum_pass_first(
     float* __restrict__ dst, const float* __restrict__ src, int64_t len_out, int L, int G, int q,
@@ -412,9 +413,9 @@ rise_status launch_iterate_sum(float* out, const float* in, int64_t n, int64_t m
     else if (n == 5)
       hipLaunchKernelGGL(iterate_sum_pass_first<5>, grid, block, 0, s, dst, src, p.len_out, p.L,
                          p.G, p.q, v);
-    else if (n == 6)
+    else if (n == 6)  // a group per 16 + 8-byte load pair beats units of two groups
       hipLaunchKernelGGL(iterate_sum_pass_first<6>, grid, block, 0, s, dst, src, p.len_out, p.L,
-                         p.G, p.q, v);
+                         p.G, p.q, 0);
     else if (n == 7)
       hipLaunchKernelGGL(iterate_sum_pass_first<7>, grid, block, 0, s, dst, src, p.len_out, p.L,
                          p.G, p.q, v);
